@@ -1,0 +1,167 @@
+"""FP64 oracle for separable non-local means -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library never calls it, and the
+two share no code.
+
+The arithmetic lives in ``snlm_oracle.c`` (plain C, double precision, direct
+patch sums, ``exp`` from libm).  This module only compiles that file with gcc
+and marshals NumPy arrays into it.
+
+What it computes (Ghosh & Chaudhury, "Fast Separable Non-Local Means"):
+
+* ``nlm1d``    -- 1D NLM of eq. 1dNLM with patch distances of eq.
+  distanceSquared, computed directly, on the line extended by half-sample
+  symmetric reflection.
+* ``snlm``     -- the separable RC / CR pipelines of Sec. 3.
+* ``pixel``    -- one output pixel of ``snlm``, for sampled checks of large images.
+* ``patch_d2`` -- one patch distance (eq. distanceSquared).
+
+Pins (tests that tie it to something other than itself) live in
+``tests/test_oracle_pins.py``: hand-derived closed forms, the PatchLift
+identity computed a different way (Sec. 2.1-2.2, Alg. 1, eqs. lift and dist),
+and invariants; ``tests/test_oracle_mutants.py`` checks that planted mistakes
+in this file's C source fail those pins.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCE = os.path.join(_HERE, "snlm_oracle.c")
+_LIB = os.path.join(_HERE, "libsnlm_oracle.so")
+
+BOX, GAUSS = 0, 1
+ROW_COL, COL_ROW = 0, 1
+_KERNELS = {"box": BOX, "gauss": GAUSS, BOX: BOX, GAUSS: GAUSS}
+_ORDERS = {"row_col": ROW_COL, "col_row": COL_ROW, ROW_COL: ROW_COL, COL_ROW: COL_ROW}
+
+
+def build(force: bool = False, src: str = SOURCE, out: str = _LIB) -> str:
+    """Compile the C oracle with gcc (no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(src):
+        tmp = out + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
+               "-shared", "-fPIC", "-o", tmp, src, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, out)
+    return out
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _beta(kernel: int, K: int, beta) -> float:
+    # Gaussian width: beta = K/2 unless given (the patch kernel of Sec. 2).
+    if beta is None or beta <= 0:
+        return K / 2.0
+    return float(beta)
+
+
+class Oracle:
+    """The compiled oracle behind a small NumPy interface."""
+
+    def __init__(self, libpath: str):
+        lib = ctypes.CDLL(libpath)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L, I, D = ctypes.c_long, ctypes.c_int, ctypes.c_double
+        lib.snlm_oracle_nlm1d.argtypes = [dp, L, L, I, I, D, I, D, dp, L]
+        lib.snlm_oracle_nlm1d.restype = I
+        lib.snlm_oracle_snlm.argtypes = [dp, L, L, L, I, I, D, I, D, I, dp, I]
+        lib.snlm_oracle_snlm.restype = I
+        lib.snlm_oracle_pixel.argtypes = [dp, L, L, L, I, I, D, I, D, I, L, L]
+        lib.snlm_oracle_pixel.restype = D
+        lib.snlm_oracle_patch_d2.argtypes = [dp, L, L, L, I, I, D]
+        lib.snlm_oracle_patch_d2.restype = D
+        lib.snlm_oracle_max_threads.argtypes = []
+        lib.snlm_oracle_max_threads.restype = I
+        self._lib = lib
+        self.path = libpath
+
+    def nlm1d(self, x, S: int, K: int, h: float, kernel="box", beta=None) -> np.ndarray:
+        """1D NLM (eq. 1dNLM) of a line, in float64."""
+        k = _KERNELS[kernel]
+        xa = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+        y = np.empty_like(xa)
+        rc = self._lib.snlm_oracle_nlm1d(_ptr(xa), xa.size, 1, S, K, float(h), k,
+                                         _beta(k, K, beta), _ptr(y), 1)
+        if rc != 0:
+            raise ValueError("oracle rejected the arguments")
+        return y
+
+    def snlm(self, f, S: int, K: int, h: float, kernel="box", order="row_col", beta=None,
+             threads: int = 0) -> np.ndarray:
+        """Separable NLM (Sec. 3, RC or CR) of a 2D image, in float64."""
+        k = _KERNELS[kernel]
+        fa = np.ascontiguousarray(np.asarray(f, dtype=np.float64))
+        if fa.ndim != 2:
+            raise ValueError("expected a 2D image")
+        H, W = fa.shape
+        out = np.empty_like(fa)
+        nt = threads if threads > 0 else self.max_threads()
+        rc = self._lib.snlm_oracle_snlm(_ptr(fa), H, W, W, S, K, float(h), k,
+                                        _beta(k, K, beta), _ORDERS[order], _ptr(out), nt)
+        if rc != 0:
+            raise ValueError("oracle rejected the arguments")
+        return out
+
+    def pixel(self, f, r: int, c: int, S: int, K: int, h: float, kernel="box",
+              order="row_col", beta=None) -> float:
+        """One output pixel of ``snlm`` computed from the input alone."""
+        k = _KERNELS[kernel]
+        fa = np.ascontiguousarray(np.asarray(f, dtype=np.float64))
+        H, W = fa.shape
+        v = self._lib.snlm_oracle_pixel(_ptr(fa), H, W, W, S, K, float(h), k,
+                                        _beta(k, K, beta), _ORDERS[order], int(r), int(c))
+        if np.isnan(v):
+            raise ValueError("oracle rejected the arguments")
+        return float(v)
+
+    def patch_d2(self, x, i: int, j: int, K: int, kernel="box", beta=None) -> float:
+        """Patch distance of eq. distanceSquared on the reflected extension of ``x``."""
+        k = _KERNELS[kernel]
+        xa = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+        return float(self._lib.snlm_oracle_patch_d2(_ptr(xa), xa.size, int(i), int(j), K, k,
+                                                    _beta(k, K, beta)))
+
+    def max_threads(self) -> int:
+        """Threads an OpenMP region of the oracle uses by default."""
+        return int(self._lib.snlm_oracle_max_threads())
+
+
+_default = None
+
+
+def load(libpath: str | None = None) -> Oracle:
+    """The oracle built from ``snlm_oracle.c`` (or a given compiled copy)."""
+    global _default
+    if libpath is not None:
+        return Oracle(libpath)
+    if _default is None:
+        _default = Oracle(build())
+    return _default
+
+
+def nlm1d(*a, **k):
+    return load().nlm1d(*a, **k)
+
+
+def snlm(*a, **k):
+    return load().snlm(*a, **k)
+
+
+def pixel(*a, **k):
+    return load().pixel(*a, **k)
+
+
+def patch_d2(*a, **k):
+    return load().patch_d2(*a, **k)
+
+
+def max_threads() -> int:
+    return load().max_threads()

@@ -1,0 +1,200 @@
+/*
+ * FP64 oracle for separable non-local means (Ghosh & Chaudhury, "Fast Separable
+ * Non-Local Means").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may call, link or load
+ * this file; it exists so that tests, the smoke check and the CPU baseline of
+ * the benchmark can compare the GPU library against a plain, slow, obviously
+ * correct computation.  It shares no code, header, table or helper with the GPU
+ * library.
+ *
+ * What it computes (all in double precision, 0-based indices):
+ *
+ *   patch distance  (Sec. 2, eq. distanceSquared)
+ *       d2(i,j) = sum_{k=-K..K} g(k) * (x_e(i+k) - x_e(j+k))^2
+ *   patch kernel    (Sec. 2, definition of g_beta under eq. distanceSquared)
+ *       box: g(k) = 1 ;  gauss: g(k) = exp(-k^2 / (2 beta^2)), g(0) = 1
+ *   1D NLM          (Sec. 2, eq. 1dNLM)
+ *       y(i) = sum_{j=i-S..i+S} w(i,j) x_e(j) / sum_{j=i-S..i+S} w(i,j),
+ *       w(i,j) = exp(-d2(i,j) / h^2)
+ *   separable NLM   (Sec. 3, the RC and CR pipelines)
+ *       row_col: filter every row, then every column of the row-filtered image
+ *       col_row: filter every column, then every row of the column-filtered image
+ *
+ * Readings where the paper is silent:
+ *   - x_e is the line extended by half-sample symmetric reflection
+ *     (... x1 x0 | x0 x1 ... x_{N-1} | x_{N-1} x_{N-2} ...), applied to patch
+ *     taps and to the search window alike, with period 2N so that lines shorter
+ *     than the reach S+K are handled.  Sec. 2 only notes that the signal is
+ *     assumed extended beyond its ends.
+ *   - h = +inf gives w = 1 everywhere.  w(i,i) = 1 for every h > 0, and any pair
+ *     with d2 = 0 has w = 1 (exp(-0/h^2) = 1), written out explicitly so that a
+ *     tiny h whose square underflows does not turn 0/0 into NaN.
+ *   - For the Gaussian kernel beta defaults to K/2 (the caller passes beta).
+ *
+ * Distances are computed literally from their definition (no lifting, no
+ * running sums), so the cost is O(N S K) per line.  Threads, when asked for,
+ * split independent lines; they never change the arithmetic of a pixel.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORACLE_BOX 0
+#define ORACLE_GAUSS 1
+#define ORACLE_ROW_COL 0
+#define ORACLE_COL_ROW 1
+
+/* Half-sample symmetric reflection of index t into [0, n), period 2n. */
+static long refl(long t, long n) {
+    long p = 2 * n;
+    long m = t % p;
+    if (m < 0) m += p;
+    return m < n ? m : p - 1 - m;
+}
+
+/* Patch kernel tap g(k) (Sec. 2). */
+static double tap(int k, int kernel, double beta) {
+    if (kernel == ORACLE_BOX || k == 0) return 1.0;
+    return exp(-((double)k * (double)k) / (2.0 * beta * beta));
+}
+
+/* Weighted squared distance between the patches centred at i and j of the
+ * extended line (eq. distanceSquared). */
+static double patch_d2(const double *x, long n, long stride, long i, long j, int K,
+                       int kernel, double beta) {
+    double d2 = 0.0;
+    for (int k = -K; k <= K; ++k) {
+        double a = x[refl(i + k, n) * stride];
+        double b = x[refl(j + k, n) * stride];
+        d2 += tap(k, kernel, beta) * (a - b) * (a - b);
+    }
+    return d2;
+}
+
+/* One output sample of the 1D NLM of a strided line (eq. 1dNLM). */
+static double nlm1d_at(const double *x, long n, long stride, long i, int S, int K,
+                       double h, int kernel, double beta) {
+    double P = 0.0, Q = 0.0;
+    for (long j = i - S; j <= i + S; ++j) {
+        double d2 = patch_d2(x, n, stride, i, j, K, kernel, beta);
+        double w;
+        if (d2 == 0.0)
+            w = 1.0;
+        else
+            w = exp(-d2 / (h * h));
+        P += w * x[refl(j, n) * stride];
+        Q += w;
+    }
+    return P / Q;
+}
+
+static int bad_args(long n, int S, int K, double h, int kernel, double beta) {
+    if (n < 1 || S < 0 || K < 0) return 1;
+    if (!(h > 0.0)) return 1; /* rejects NaN too */
+    if (kernel != ORACLE_BOX && kernel != ORACLE_GAUSS) return 1;
+    if (kernel == ORACLE_GAUSS && K > 0 && !(beta > 0.0)) return 1;
+    return 0;
+}
+
+/* Patch distance d2(i, j) of a contiguous line, i and j any integers (the line
+ * is extended by reflection). */
+double snlm_oracle_patch_d2(const double *x, long n, long i, long j, int K, int kernel,
+                            double beta) {
+    if (!x || n < 1 || K < 0) return NAN;
+    if (kernel != ORACLE_BOX && kernel != ORACLE_GAUSS) return NAN;
+    return patch_d2(x, n, 1, i, j, K, kernel, beta);
+}
+
+/* 1D NLM of a whole line: y[i*ystride] for i in [0, n). */
+int snlm_oracle_nlm1d(const double *x, long n, long stride, int S, int K, double h,
+                      int kernel, double beta, double *y, long ystride) {
+    if (!x || !y || bad_args(n, S, K, h, kernel, beta)) return -1;
+    for (long i = 0; i < n; ++i)
+        y[i * ystride] = nlm1d_at(x, n, stride, i, S, K, h, kernel, beta);
+    return 0;
+}
+
+/* Filter every row (rows=1) or every column (rows=0) of an H x W image with
+ * row pitch ld (elements), writing an H x W image with pitch ldo. */
+static void filter_lines(const double *in, long H, long W, long ld, int rows, int S,
+                         int K, double h, int kernel, double beta, double *out,
+                         long ldo, int nthreads) {
+    long nlines = rows ? H : W;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1)
+#endif
+    for (long l = 0; l < nlines; ++l) {
+        if (rows)
+            snlm_oracle_nlm1d(in + l * ld, W, 1, S, K, h, kernel, beta, out + l * ldo, 1);
+        else
+            snlm_oracle_nlm1d(in + l, H, ld, S, K, h, kernel, beta, out + l, ldo);
+    }
+    (void)nthreads;
+}
+
+/* Separable NLM of an H x W image (Sec. 3).  order: 0 = row_col, 1 = col_row.
+ * out has pitch W.  Returns 0, or -1 on bad arguments / allocation failure. */
+int snlm_oracle_snlm(const double *f, long H, long W, long ld, int S, int K, double h,
+                     int kernel, double beta, int order, double *out, int nthreads) {
+    if (!f || !out || H < 1 || W < 1 || ld < W) return -1;
+    if (bad_args(H, S, K, h, kernel, beta) || bad_args(W, S, K, h, kernel, beta)) return -1;
+    if (order != ORACLE_ROW_COL && order != ORACLE_COL_ROW) return -1;
+    double *mid = (double *)malloc(sizeof(double) * (size_t)H * (size_t)W);
+    if (!mid) return -1;
+    int first_rows = (order == ORACLE_ROW_COL);
+    filter_lines(f, H, W, ld, first_rows, S, K, h, kernel, beta, mid, W, nthreads);
+    filter_lines(mid, H, W, W, !first_rows, S, K, h, kernel, beta, out, W, nthreads);
+    free(mid);
+    return 0;
+}
+
+/* One output pixel (r, c) of the separable NLM, computed from the input alone:
+ * the second pass at (r, c) needs the first-pass output along line r or c at
+ * the reflected positions within reach S+K, and each of those is one sample of
+ * a first-pass 1D NLM.  Used to check large images at sampled pixels. */
+double snlm_oracle_pixel(const double *f, long H, long W, long ld, int S, int K,
+                         double h, int kernel, double beta, int order, long r, long c) {
+    if (!f || H < 1 || W < 1 || ld < W || r < 0 || r >= H || c < 0 || c >= W) return NAN;
+    if (bad_args(H, S, K, h, kernel, beta) || bad_args(W, S, K, h, kernel, beta)) return NAN;
+    int reach = S + K;
+    if (order == ORACLE_ROW_COL) {
+        /* second pass runs along column c; first pass along rows at column c */
+        double *col = (double *)malloc(sizeof(double) * (size_t)H);
+        if (!col) return NAN;
+        for (long t = 0; t < H; ++t) col[t] = NAN;
+        for (long m = r - reach; m <= r + reach; ++m) {
+            long rr = refl(m, H);
+            if (isnan(col[rr]))
+                col[rr] = nlm1d_at(f + rr * ld, W, 1, c, S, K, h, kernel, beta);
+        }
+        double v = nlm1d_at(col, H, 1, r, S, K, h, kernel, beta);
+        free(col);
+        return v;
+    } else if (order == ORACLE_COL_ROW) {
+        double *row = (double *)malloc(sizeof(double) * (size_t)W);
+        if (!row) return NAN;
+        for (long t = 0; t < W; ++t) row[t] = NAN;
+        for (long m = c - reach; m <= c + reach; ++m) {
+            long cc = refl(m, W);
+            if (isnan(row[cc]))
+                row[cc] = nlm1d_at(f + cc, H, ld, r, S, K, h, kernel, beta);
+        }
+        double v = nlm1d_at(row, W, 1, c, S, K, h, kernel, beta);
+        free(row);
+        return v;
+    }
+    return NAN;
+}
+
+/* Number of threads an OpenMP region would use (1 without OpenMP). */
+int snlm_oracle_max_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,237 @@
+"""Checks that tie the FP64 oracle to things other than itself.
+
+Each ``check_*`` takes an ``oracle.Oracle`` and raises AssertionError when the
+oracle disagrees with what the paper or the mathematics fixes.  They are run
+against the real oracle (tests/test_oracle_pins.py) and against copies of it
+with planted mistakes (tests/test_oracle_mutants.py), which must each fail at
+least one check.
+"""
+from __future__ import annotations
+
+import math
+import os
+
+import numpy as np
+from scipy.ndimage import uniform_filter1d
+
+import patchlift_ref as pl
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+_MATH = {k: getattr(math, k) for k in ("exp", "log", "sqrt")}
+_MATH["e"] = math.e
+
+
+def _eval(expr: str, env: dict) -> float:
+    return float(eval(expr, {"__builtins__": {}}, {**_MATH, **env}))
+
+
+def _parse_blocks(path: str):
+    blocks, cur = [], None
+    for raw in open(path):
+        line = raw.strip()
+        if not line or line.startswith("#"):
+            continue
+        key, _, val = line.partition(":")
+        val = val.strip()
+        if key == "case":
+            cur = {"case": val, "define": []}
+            blocks.append(cur)
+        elif key == "define":
+            cur["define"].append(val)
+        elif key != "why":
+            cur[key] = val
+    return blocks
+
+
+def _params(s: str) -> dict:
+    out = {}
+    for tok in s.split():
+        k, v = tok.split("=")
+        out[k] = v if k == "kernel" else float(v)
+    return out
+
+
+def check_worked_examples_1d(orc):
+    for b in _parse_blocks(os.path.join(GOLDEN, "worked_examples.txt")):
+        x = [float(v) for v in b["x"].split()]
+        p = _params(b["params"])
+        want = [_eval(e, {}) for e in b["expect"].split(";")]
+        got = orc.nlm1d(x, int(p["S"]), int(p["K"]), p["h"], p["kernel"], p.get("beta"))
+        assert np.allclose(got, want, rtol=0, atol=1e-13), (b["case"], got, want)
+
+
+def check_separable_2x2(orc):
+    path = os.path.join(GOLDEN, "separable_2x2.txt")
+    text = {}
+    defs = []
+    for raw in open(path):
+        line = raw.strip()
+        if not line or line.startswith("#"):
+            continue
+        key, _, val = line.partition(":")
+        if key == "define":
+            defs.append(val.strip())
+        else:
+            text[key] = val.strip()
+    env = {}
+    for d in defs:
+        name, expr = d.split("=", 1)
+        env[name.strip()] = _eval(expr, env)
+    f = np.array([[float(v) for v in row.split()] for row in text["f"].split(";")])
+    p = _params(text["params"])
+    for order in ("row_col", "col_row"):
+        want = np.array([[_eval(e, env) for e in row.split(",")]
+                         for row in text["expect_" + order].split(";")])
+        got = orc.snlm(f, int(p["S"]), int(p["K"]), p["h"], p["kernel"], order)
+        assert np.allclose(got, want, rtol=0, atol=1e-13), (order, got, want)
+
+
+def check_alg1_distances(orc, seed: int = 7):
+    """Alg. 1 + eq. dist (zero extension) == direct distances, exactly, on
+    integer signals with the box kernel; the oracle sees the signal embedded in
+    zeros so that no reflection is involved."""
+    rng = np.random.default_rng(seed)
+    for (N, S, K) in [(8, 2, 1), (13, 4, 3), (20, 5, 2), (9, 3, 0)]:
+        x = rng.integers(-9, 10, N).astype(np.float64)
+        d = pl.alg1_distances(x, S, K, "box")
+        big = np.concatenate([np.zeros(K), x, np.zeros(K)])
+        for (i, j), v in d.items():
+            assert orc.patch_d2(big, i + K, j + K, K, "box") == v, (N, S, K, i, j)
+    # Gaussian taps: agreement to rounding
+    x = rng.normal(size=15)
+    d = pl.alg1_distances(x, 4, 3, "gauss", 1.5)
+    big = np.concatenate([np.zeros(3), x, np.zeros(3)])
+    for (i, j), v in d.items():
+        ref = orc.patch_d2(big, i + 3, j + 3, 3, "gauss", 1.5)
+        assert abs(ref - v) <= 1e-12 * max(1.0, abs(ref)), (i, j, ref, v)
+
+
+def check_difference_lift(orc, seed: int = 11):
+    """Difference-lift prefix sums (eq. recursion) on the reflected extension ==
+    direct distances: exact for integer signals and the box kernel."""
+    rng = np.random.default_rng(seed)
+    for (N, S, K) in [(1, 3, 2), (2, 4, 1), (7, 5, 3), (16, 6, 4), (25, 3, 0)]:
+        x = rng.integers(-20, 21, N).astype(np.float64)
+        d = pl.difference_lift_distances(x, S, K, "box")
+        for s in range(S + 1):
+            for t in range(-S, N):
+                assert orc.patch_d2(x, t, t + s, K, "box") == d[s, t + S], (N, S, K, s, t)
+    x = rng.normal(size=12) * 50
+    d = pl.difference_lift_distances(x, 4, 3, "gauss", 1.5)
+    for s in range(5):
+        for t in range(-4, 12):
+            ref = orc.patch_d2(x, t, t + s, 3, "gauss", 1.5)
+            assert abs(ref - d[s, t + 4]) <= 1e-11 * max(1.0, ref), (s, t)
+
+
+def check_patchlift_nlm(orc, seed: int = 3):
+    """PatchLift-NLM (Alg. 2, symmetric pair weights) and direct NLM agree to
+    rounding; on the setting of the paper's 1D experiment (sigma = 0.2, S = 10,
+    K = 5, h = 1) their mean squared difference is of order 1e-17 or below."""
+    rng = np.random.default_rng(seed)
+    for kernel in ("box", "gauss"):
+        x = rng.normal(size=40) * 30 + 100
+        a = orc.nlm1d(x, 6, 2, 40.0, kernel)
+        b = pl.patchlift_nlm1d(x, 6, 2, 40.0, kernel)
+        assert np.max(np.abs(a - b)) <= 1e-11, kernel
+    from paper_1407_2343_amd.synth import noisy_line
+    x = noisy_line(400, 0.2, seed)
+    a = orc.nlm1d(x, 10, 5, 1.0, "box")
+    b = pl.patchlift_nlm1d(x, 10, 5, 1.0, "box")
+    assert np.mean((a - b) ** 2) < 1e-17
+
+
+def _img(seed, H=23, W=31):
+    rng = np.random.default_rng(seed)
+    return rng.normal(size=(H, W)) * 25 + 120
+
+
+def check_constant(orc):
+    f = np.full((9, 14), 77.25)
+    for kernel in ("box", "gauss"):
+        for order in ("row_col", "col_row"):
+            assert np.array_equal(orc.snlm(f, 3, 2, 10.0, kernel, order), f)
+
+
+def check_h_inf_box_average(orc):
+    """h = inf: all weights are 1, so each pass is a (2S+1)-tap moving average of
+    the symmetric extension (scipy's 'reflect' mode is that extension)."""
+    f = _img(1)
+    for S in (1, 4):
+        want = uniform_filter1d(uniform_filter1d(f, 2 * S + 1, axis=1, mode="reflect"),
+                                2 * S + 1, axis=0, mode="reflect")
+        got = orc.snlm(f, S, 2, math.inf, "box", "row_col")
+        assert np.max(np.abs(got - want)) < 1e-10
+        got = orc.snlm(f, S, 3, math.inf, "gauss", "col_row")
+        want = uniform_filter1d(uniform_filter1d(f, 2 * S + 1, axis=0, mode="reflect"),
+                                2 * S + 1, axis=1, mode="reflect")
+        assert np.max(np.abs(got - want)) < 1e-10
+
+
+def check_h_zero_identity(orc):
+    f = _img(2)
+    for kernel in ("box", "gauss"):
+        got = orc.snlm(f, 4, 2, 1e-4, kernel, "row_col")
+        assert np.max(np.abs(got - f)) < 1e-12
+
+
+def check_s0_identity(orc):
+    f = _img(3)
+    assert np.array_equal(orc.snlm(f, 0, 3, 50.0, "box", "row_col"), f)
+
+
+def check_flips(orc):
+    f = _img(4)
+    for kernel in ("box", "gauss"):
+        base = orc.snlm(f, 4, 2, 60.0, kernel, "row_col")
+        for ax in ((0,), (1,), (0, 1)):
+            got = orc.snlm(np.flip(f, ax), 4, 2, 60.0, kernel, "row_col")
+            assert np.max(np.abs(got - np.flip(base, ax))) < 1e-10, (kernel, ax)
+
+
+def check_transpose(orc):
+    f = _img(5)
+    a = orc.snlm(f, 3, 2, 50.0, "gauss", "row_col")
+    b = orc.snlm(f.T, 3, 2, 50.0, "gauss", "col_row").T
+    assert np.array_equal(a, b)
+
+
+def check_affine(orc):
+    """NLM(a X + b; |a| h) = a NLM(X; h) + b, since d2 scales by a^2."""
+    f = _img(6)
+    for a_, b_ in ((2.5, -7.0), (-0.5, 3.0)):
+        lhs = orc.snlm(a_ * f + b_, 3, 2, 55.0 * abs(a_), "box", "row_col")
+        rhs = a_ * orc.snlm(f, 3, 2, 55.0, "box", "row_col") + b_
+        assert np.max(np.abs(lhs - rhs)) < 1e-9
+
+
+def check_k0_pixel_filter(orc):
+    """K = 0: d2 = (x_i - x_j)^2, the neighbourhood (Yaroslavsky) filter."""
+    rng = np.random.default_rng(8)
+    x = rng.normal(size=30) * 20
+    S, h = 4, 15.0
+    idx = np.arange(-S, x.size + S)
+    m = np.mod(idx, 2 * x.size)
+    xe = x[np.where(m < x.size, m, 2 * x.size - 1 - m)]
+    want = np.empty_like(x)
+    for i in range(x.size):
+        win = xe[i:i + 2 * S + 1]
+        w = np.exp(-(x[i] - win) ** 2 / h ** 2)
+        want[i] = np.sum(w * win) / np.sum(w)
+    assert np.max(np.abs(orc.nlm1d(x, S, 0, h, "box") - want)) < 1e-12
+
+
+def check_pixel_matches_full(orc):
+    f = _img(9, 17, 12)
+    for order in ("row_col", "col_row"):
+        full = orc.snlm(f, 5, 2, 40.0, "gauss", order)
+        for (r, c) in ((0, 0), (16, 11), (8, 3), (1, 10)):
+            assert orc.pixel(f, r, c, 5, 2, 40.0, "gauss", order) == full[r, c]
+
+
+ALL_CHECKS = [
+    check_worked_examples_1d, check_separable_2x2, check_alg1_distances,
+    check_difference_lift, check_patchlift_nlm, check_constant, check_h_inf_box_average,
+    check_h_zero_identity, check_s0_identity, check_flips, check_transpose, check_affine,
+    check_k0_pixel_filter, check_pixel_matches_full,
+]

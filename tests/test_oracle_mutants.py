@@ -1,0 +1,50 @@
+"""Planted mistakes in the oracle's C source must each fail at least one pin.
+
+Every mutant is a copy of oracle/snlm_oracle.c with one plausible mistake (a
+dropped tap, a wrong extension, a wrong sign or index, swapped passes), built
+into a temporary library on the CPU.  The real oracle is never modified."""
+import os
+
+import pytest
+
+import oracle
+import oracle_pin_checks as pc
+
+MUTANTS = {
+    "drop_last_tap": ("for (int k = -K; k <= K; ++k)", "for (int k = -K; k < K; ++k)"),
+    "periodic_instead_of_reflect": ("return m < n ? m : p - 1 - m;", "return m < n ? m : m - n;"),
+    "exp_wrong_scale": ("w = exp(-d2 / (h * h));", "w = exp(-d2 / h);"),
+    "exp_wrong_sign": ("w = exp(-d2 / (h * h));", "w = exp(d2 / (h * h));"),
+    "value_from_centre": ("P += w * x[refl(j, n) * stride];", "P += w * x[refl(i, n) * stride];"),
+    "mirrored_partner_tap": ("double b = x[refl(j + k, n) * stride];",
+                             "double b = x[refl(j - k, n) * stride];"),
+    "gauss_width": ("(2.0 * beta * beta)", "(beta * beta)"),
+    "window_one_short": ("for (long j = i - S; j <= i + S; ++j)", "for (long j = i - S; j < i + S; ++j)"),
+    "second_pass_reads_input": (
+        "filter_lines(mid, H, W, W, !first_rows, S, K, h, kernel, beta, out, W, nthreads);",
+        "filter_lines(f, H, W, ld, !first_rows, S, K, h, kernel, beta, out, W, nthreads);"),
+    "orders_swapped": ("int first_rows = (order == ORACLE_ROW_COL);",
+                       "int first_rows = (order != ORACLE_ROW_COL);"),
+    "normaliser_off_by_one": ("return P / Q;", "return P / (Q + 1.0);"),
+    "tap_difference_unsquared": ("d2 += tap(k, kernel, beta) * (a - b) * (a - b);",
+                                 "d2 += tap(k, kernel, beta) * (a - b);"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(tmp_path, name):
+    old, new = MUTANTS[name]
+    src = open(oracle.SOURCE).read()
+    assert src.count(old) >= 1, name
+    mutated = src.replace(old, new)
+    srcp = os.path.join(tmp_path, "mutant.c")
+    open(srcp, "w").write(mutated)
+    lib = oracle.build(force=True, src=srcp, out=os.path.join(tmp_path, "libmutant.so"))
+    orc = oracle.load(lib)
+    failed = []
+    for check in pc.ALL_CHECKS:
+        try:
+            check(orc)
+        except (AssertionError, ValueError, IndexError):
+            failed.append(check.__name__)
+    assert failed, "mutant %s passed every pin" % name
