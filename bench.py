@@ -1,0 +1,350 @@
+"""Benchmark of separable PatchLift NLM on one MI355X.
+
+One step = one batched launch over the ragged batch workload: 64 FP32 images,
+H and W drawn log-uniform in [128, 1024] per axis, sigma drawn from
+{10, 20, 30, 40} per image with h = 10 sigma, S = 10, K = 3, box patch kernel,
+rows then columns.  Every step runs the whole hot path: reflected loads,
+lifting, diagonal running sums, weights, accumulation and normalisation for
+both passes of all 64 images, as two persistent launches replayed from one HIP
+graph.  Inputs are resident in HBM before timing starts.
+
+The JSON line also carries: the plain single-image launches (the same 64
+images one by one, and one 512 x 512 image in the four kernel/order
+variants), the roofline of the batched kernels (device time from HIP events
+on the stream they run on), the serving workload (2000 requests, Poisson
+arrivals, p50/p99 latency and Mpixel/s, against FIFO plain launches), the
+precision variants on a 4096 x 4096 image, and the FP64 oracle timed on the
+host cores on a bounded sample of the batch (``cpu_baseline``).
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-serve] [--no-precision] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+S, K = 10, 3
+# VALU issue peak of MI355X without packed FP32 (not used by this build):
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-instructions/s.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Algorithmic VALU lane-instructions per unordered pair (u, u+s) of one pass,
+# box kernel, on the scaled samples: one lifted difference, two fused
+# multiply-adds for the window recursion (entering and leaving term), two fused
+# multiply-adds and two adds for the two accumulations.  The exp runs on the
+# transcendental unit alongside (measured: a 1:7 mix of v_exp_f32 and FMA
+# issues at 67.5 lane-ops/CU/clock, above the 64 of VALU alone), so it is not
+# counted against the VALU issue peak; its rate is reported separately.
+PAIR_VALU = 7
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_steps(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall / steps * 1e3
+
+
+def cpu_baseline(items, budget_s: float = 12.0):
+    """The FP64 oracle on the first images of the batch until ~budget_s of
+    wall time, with every host core."""
+    import oracle
+    orc = oracle.load()
+    px = 0
+    t0 = time.perf_counter()
+    n = 0
+    for img, sig in items:
+        orc.snlm(img.astype(np.float64), S, K, 10.0 * sig, "box", "row_col")
+        px += img.size
+        n += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": round(px / dt / 1e6, 4), "unit": "Mpixel/s", "cores": orc.max_threads(),
+            "kind": "oracle",
+            "sample": "first %d of the 64 batch images (%d px), FP64 direct separable NLM, "
+                      "S=10 K=3 box row_col, %.1f s wall" % (n, px, dt)}
+
+
+def traffic_from_profiles():
+    """HBM bytes per batched step from the committed counter summary, if it was
+    taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic_batch.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, "paper_1407_2343_amd", "csrc", "snlm_device.hpp"), "rb").read()
+    if rec.get("device_source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return rec.get("hbm_bytes_per_step")
+
+
+# ----------------------------------------------------------------- serving --
+def serving(torch, snlm, n_req=2000, rate_frac=0.7, seed=4000):
+    """2000 requests (sizes log-uniform 64..2048 per axis, sigma U[10,40],
+    S in {5,10,15}, K in {2,3,4}, box/Gauss and both orders 50/50), inputs
+    generated on the device before timing.  Saturation throughput first (all
+    requests at t = 0), then Poisson arrivals at rate_frac of it; p50/p99 of
+    submit-to-completion latency.  Baseline: the same arrivals served FIFO by
+    plain single-image launches, one at a time."""
+    from paper_1407_2343_amd.synth import clean_image, serving_requests
+    reqs = serving_requests(n_req, seed=seed, rate_per_s=1.0)
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(seed)
+    pool = [torch.from_numpy(clean_image(2048, 2048, np.random.default_rng(seed + i))).to("cuda:0")
+            .to(torch.float32) for i in range(4)]
+    rng = np.random.default_rng(seed + 7)
+    xs, outs = [], []
+    for i, r in enumerate(reqs):
+        base = pool[i % 4]
+        y0 = int(rng.integers(0, 2048 - r["H"] + 1))
+        x0 = int(rng.integers(0, 2048 - r["W"] + 1))
+        noise = torch.randn((r["H"], r["W"]), generator=g, device="cuda:0")
+        xs.append((base[y0:y0 + r["H"], x0:x0 + r["W"]] + r["sigma"] * noise).contiguous())
+        outs.append(torch.empty((r["H"], r["W"]), dtype=torch.float32, device="cuda:0"))
+    torch.cuda.synchronize()
+    total_px = sum(r["H"] * r["W"] for r in reqs)
+    arena = 512 << 20  # HBM budget of in-flight intermediates
+    srv = snlm.Context(arena_bytes=arena)
+    jobs = [srv.job_for(x, o, r["S"], r["K"], 10.0 * r["sigma"], r["kernel"], r["order"])
+            for x, o, r in zip(xs, outs, reqs)]
+
+    def run(arrivals, count):
+        t_start = time.perf_counter()
+        tickets = []
+        for j, a in zip(jobs[:count], arrivals):
+            while time.perf_counter() - t_start < a:
+                pass
+            tickets.append(srv.submit(j))
+        lat, first, last = [], None, None
+        pending = list(tickets)
+        while pending:
+            rest = []
+            for t in pending:
+                ts, ta, td = srv.job_times(t)
+                if td > 0:
+                    st = srv.poll(t)
+                    if st != snlm.OK:
+                        raise RuntimeError("served job failed: %d %s" % (st, srv.last_error()))
+                    lat.append((td - ts) / 1e3)
+                    first = ts if first is None else min(first, ts)
+                    last = td if last is None else max(last, td)
+                else:
+                    rest.append(t)
+            pending = rest
+            if pending:
+                time.sleep(0.0002)
+        return np.array(lat), (last - first) / 1e6
+
+    run([0.0] * 64, 64)  # warm every kernel class once
+    lat_sat, span_sat = run([0.0] * n_req, n_req)
+    sat_rate = n_req / span_sat
+    rate = rate_frac * sat_rate
+    arr_rng = np.random.default_rng(seed + 11)
+    arrivals = np.cumsum(arr_rng.exponential(1.0 / rate, n_req))
+    lat, span = run(list(arrivals), n_req)
+    srv.close()
+
+    # FIFO plain launches at the same arrival times
+    plain = snlm.Context(arena_bytes=arena)
+    for j in jobs[:64]:
+        plain.denoise_job(j)
+    plain.sync()
+    t_start = time.perf_counter()
+    plat = []
+    for j, a in zip(jobs, arrivals):
+        while time.perf_counter() - t_start < a:
+            pass
+        plain.denoise_job(j)
+        plain.sync()
+        plat.append((time.perf_counter() - t_start - a) * 1e3)
+    plain_span = time.perf_counter() - t_start
+    plain.close()
+    plat = np.array(plat)
+    return {
+        "requests": n_req, "pixels": int(total_px), "arena_bytes": arena,
+        "saturation_req_per_s": round(sat_rate, 1),
+        "saturation_mpx_per_s": round(total_px / span_sat / 1e6, 1),
+        "rate_req_per_s": round(rate, 1),
+        "p50_ms": round(float(np.percentile(lat, 50)), 3),
+        "p99_ms": round(float(np.percentile(lat, 99)), 3),
+        "mpx_per_s": round(total_px / span / 1e6, 1),
+        "plain_fifo_p50_ms": round(float(np.percentile(plat, 50)), 3),
+        "plain_fifo_p99_ms": round(float(np.percentile(plat, 99)), 3),
+        "plain_fifo_mpx_per_s": round(total_px / plain_span / 1e6, 1),
+    }
+
+
+# --------------------------------------------------------------- precision --
+def precision(torch, snlm, n=4096, sigma=30.0, nsample=24):
+    """4096 x 4096, sigma 30, S=15, K=4, box: {FP16, FP32 storage} x
+    {block-restarted, plain, Kahan} running sums; max-abs and RMS error at
+    sampled pixels against the FP64 oracle on the values the GPU read, and for
+    FP16 also against the FP32 input before rounding."""
+    import oracle
+    from paper_1407_2343_amd.synth import noisy_image
+    img = noisy_image(n, n, sigma, seed=3001)
+    rng = np.random.default_rng(5)
+    pts = [(0, 0), (n - 1, n - 1), (0, n - 1), (n - 1, 0)] + [
+        (int(rng.integers(0, n)), int(rng.integers(0, n))) for _ in range(nsample - 4)]
+    ctx = snlm.Context(arena_bytes=snlm.workspace_bytes(n, n) + (1 << 20))
+    ref32 = None
+    out = {}
+    for dtype in ("f32", "f16"):
+        x = torch.from_numpy(img.astype(np.float16 if dtype == "f16" else np.float32)).to("cuda:0")
+        xr = x.cpu().numpy().astype(np.float64)
+        ref = np.array([oracle.pixel(xr, r, c, 15, 4, 10 * sigma, "box", "row_col") for r, c in pts])
+        if dtype == "f32":
+            ref32 = ref
+        for sm in ("block", "plain", "kahan"):
+            y_t = torch.empty((n, n), device="cuda:0")
+            j = ctx.job_for(x, y_t, 15, 4, 10 * sigma, "box", "row_col", sm)
+            ms, _ = time_steps(torch, lambda: ctx.denoise_job(j), 3, 1)
+            y = y_t.cpu().numpy().astype(np.float64)
+            got = np.array([y[r, c] for r, c in pts])
+            e = got - ref
+            rec = {"max_abs": float(np.max(np.abs(e))), "rms": float(np.sqrt(np.mean(e * e))),
+                   "mpx_per_s": round(n * n / ms / 1e3, 1)}
+            if dtype == "f16":
+                e2 = got - ref32
+                rec["max_abs_vs_unrounded"] = float(np.max(np.abs(e2)))
+                rec["rms_vs_unrounded"] = float(np.sqrt(np.mean(e2 * e2)))
+            out["%s_%s" % (dtype, sm)] = rec
+    ctx.close()
+    return {"image": "%dx%d sigma=%g S=15 K=4 box row_col" % (n, n, sigma),
+            "sampled_pixels": len(pts), "variants": out}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(independent images would shard across GPUs with no exchange).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1407_2343_amd as snlm
+    from paper_1407_2343_amd.synth import batch_workload, noisy_image
+
+    assert torch.cuda.is_available(), "no GPU"
+    torch.cuda.set_device(0)
+    log("generating the batch workload")
+    items = batch_workload(64, 128, 1024, seed=2000)
+    xs = [torch.from_numpy(img).to("cuda:0") for img, _ in items]
+    hs = [10.0 * sig for _, sig in items]
+    total_px = sum(x.numel() for x in xs)
+    outs = [torch.empty_like(x) for x in xs]
+    ctx = snlm.Context(arena_bytes=sum(snlm.workspace_bytes(*x.shape) for x in xs) + (1 << 20))
+    jobs = snlm.job_array([ctx.job_for(x, o, S, K, h, "box", "row_col")
+                           for x, o, h in zip(xs, outs, hs)])
+
+    def step():
+        ctx.denoise_jobs(jobs)
+
+    log("batched: warmup + timed")
+    ms_step, wall_ms = time_steps(torch, step, a.steps, a.warmup)
+    # device time of the batched launches on the stream they run on
+    ctx.timing_start()
+    for _ in range(a.steps):
+        step()
+    ctx.sync()
+    bms, bn, _, _ = ctx.timing_stop()
+    kernel_ms = bms / max(bn, 1)
+    batched_mpx = total_px / (ms_step * 1e-3) / 1e6
+
+    log("plain launches of the batch images")
+    plain_jobs = list(jobs)
+
+    def plain_step():
+        for j in plain_jobs:
+            ctx.denoise_job(j)
+
+    ms_plain, _ = time_steps(torch, plain_step, max(3, a.steps // 4), 1)
+    plain_batch_mpx = total_px / (ms_plain * 1e-3) / 1e6
+
+    x512 = torch.from_numpy(noisy_image(512, 512, 20.0, seed=1001)).to("cuda:0")
+    o512 = torch.empty_like(x512)
+    plain512 = {}
+    for kernel in ("box", "gauss"):
+        for order in ("row_col", "col_row"):
+            j512 = ctx.job_for(x512, o512, S, K, 200.0, kernel, order)
+            ms, _ = time_steps(torch, lambda: ctx.denoise_job(j512), max(20, a.steps), 3)
+            plain512["%s_%s" % (kernel, order)] = round(512 * 512 / (ms * 1e-3) / 1e6, 1)
+
+    pairs = total_px * 2 * S
+    alg_ops = pairs * PAIR_VALU
+    achieved = alg_ops / (kernel_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
+            "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+            "traffic": traffic_from_profiles(),
+            "kernel": "snlm_kernel<10,3,box> row + column persistent launches (one graph replay)",
+            "kernel_ms": round(kernel_ms, 4),
+            "alg_valu_per_pair": PAIR_VALU, "pairs_per_launch": int(pairs),
+            "exp_T_per_s": round(pairs / (kernel_ms * 1e-3) / 1e12, 3),
+            "algorithmic_hbm_bytes": int(total_px * 16),
+            "hbm_gb_per_s_algorithmic": round(total_px * 16 / (kernel_ms * 1e-3) / 1e9, 1)}
+
+    result = {
+        "metric": "Mpixel/s separable NLM S=10 K=3 (batched vs plain); p50/p99 served latency",
+        "value": round(batched_mpx, 1),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded shapes + gradient + texture + Gaussian noise)",
+        "config": {"workload": "batched: 64 FP32 images, H,W log-uniform [128,1024], "
+                               "sigma in {10,20,30,40}, h=10 sigma, S=10, K=3, box, row_col",
+                   "pixels_per_step": int(total_px), "images": len(xs)},
+        "plain_same_images_mpx": round(plain_batch_mpx, 1),
+        "plain_512_mpx": plain512,
+        "wall_ms_per_step": round(wall_ms, 4),
+        "roofline": roof,
+    }
+    ctx.close()
+    if not a.no_serve:
+        log("serving")
+        result["serving"] = serving(torch, snlm)
+    if not a.no_precision:
+        log("precision")
+        result["precision"] = precision(torch, snlm)
+    if not a.no_cpu:
+        log("cpu baseline")
+        result["cpu_baseline"] = cpu_baseline(items)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,201 @@
+/*
+ * snlm.h -- separable PatchLift non-local means on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libsnlm.so.  All pointers named "device" are device (HBM) addresses,
+ * typically the data pointers of PyTorch tensors; the caller owns them.  The
+ * library owns only its context (streams, events, graphs, small job tables,
+ * pinned staging memory and the serving thread).
+ *
+ * What is computed (Ghosh & Chaudhury, "Fast Separable Non-Local Means"):
+ *
+ *   1D NLM (Sec. 2, eq. 1dNLM), on every line of a pass:
+ *       y(i) = sum_{j=i-S..i+S} w(i,j) x(j) / sum_j w(i,j),
+ *       w(i,j) = exp(-d2(i,j) / h^2),
+ *       d2(i,j) = sum_{k=-K..K} g(k) (x(i+k) - x(j+k))^2     (eq. distanceSquared)
+ *   with g = box (1) or Gaussian exp(-k^2/(2 beta^2)) (Sec. 2), the line
+ *   extended by half-sample symmetric reflection (x1 x0 | x0 x1 ... ), and the
+ *   distances obtained by lifting each offset-s diagonal (x(t)-x(t+s))^2 and
+ *   summing it over the patch with running (prefix-difference) sums
+ *   (PatchLift, Sec. 2.1-2.2, eqs. lift and recursion; Prop. 1, Cor. 1).
+ *
+ *   Separable NLM (Sec. 3): SNLM_ROW_COL filters every row, then every column
+ *   of the row-filtered image (the RC pipeline); SNLM_COL_ROW does columns
+ *   first (CR).  The same S, K, h are used for both passes.
+ *
+ * Arithmetic is FP32 (inputs FP32 or FP16, outputs FP32).  Against an FP64
+ * evaluation of the same formulas the maximum absolute error is below 1e-3 on
+ * the [0, 255] scale for the block-restarted running sums (the default).
+ *
+ * Status codes: 0 = SNLM_OK, > 0 = SNLM_PENDING (snlm_poll only), < 0 = error.
+ * No C++ exception crosses this interface.
+ */
+#ifndef SNLM_H
+#define SNLM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SNLM_OK = 0,
+    SNLM_PENDING = 1,      /* snlm_poll: the job is still in flight */
+    SNLM_EINVAL = -1,      /* invalid argument (see each call) */
+    SNLM_ENOMEM = -2,      /* the job can never fit the arena / table capacity */
+    SNLM_EDEVICE = -3,     /* a HIP runtime error or a device-side failure */
+    SNLM_ENOTICKET = -4,   /* unknown or already collected ticket */
+    SNLM_ECLOSED = -5      /* the context is shutting down */
+};
+
+typedef enum { SNLM_BOX = 0, SNLM_GAUSS = 1 } snlm_kernel;
+typedef enum { SNLM_ROW_COL = 0, SNLM_COL_ROW = 1 } snlm_order;
+typedef enum { SNLM_F32 = 0, SNLM_F16 = 1 } snlm_dtype;
+
+/* How the box-kernel window sums along each lifted diagonal are carried
+ * (eq. recursion).  The Gaussian kernel uses an exact (2K+1)-tap FIR per
+ * diagonal and ignores this field. */
+typedef enum {
+    SNLM_SUM_BLOCK = 0,  /* recursion re-initialised every 16 samples at fixed
+                            line-relative positions (default; fastest, and
+                            results do not depend on how lines are tiled) */
+    SNLM_SUM_KAHAN = 1,  /* recursion over the whole line, Kahan-compensated */
+    SNLM_SUM_PLAIN = 2   /* recursion over the whole line, plain FP32 */
+} snlm_sum;
+
+/* Limits of the compiled kernels. */
+#define SNLM_MAX_S 16
+#define SNLM_MAX_K 8
+
+typedef struct snlm_ctx snlm_ctx;
+
+/* One denoising job.
+ *   img      device pointer, H x W, row pitch ld_in elements, FP32 or FP16
+ *   out      device pointer, H x W FP32, row pitch ld_out elements; must not
+ *            overlap img
+ *   S        search half-width, 0..SNLM_MAX_S (S = 0 returns the input)
+ *   K        patch half-width, 0..SNLM_MAX_K
+ *   h        smoothing parameter, > 0; +INFINITY gives w = 1 (moving average)
+ *   beta     Gaussian width; <= 0 selects K/2
+ *   seg_len  samples per line segment of one wave (a multiple of 16), or 0 to
+ *            let the library choose.  Results do not depend on it. */
+typedef struct {
+    const void *img;
+    float *out;
+    int H, W, ld_in, ld_out;
+    snlm_dtype dtype;
+    int S, K;
+    float h;
+    float beta;
+    snlm_kernel kernel;
+    snlm_order order;
+    snlm_sum sum;
+    int seg_len;
+} snlm_job;
+
+/* Creates a context on HIP device `device`.
+ *   stream       the caller's hipStream_t (NULL = legacy default stream);
+ *                every call is ordered after work already queued on it, and
+ *                work queued on it afterwards runs after the call's kernels
+ *   arena        caller-owned device buffer for intermediates and, when
+ *                serving, staged job images; may be NULL if arena_bytes = 0
+ *                (then only S = 0 jobs and jobs of 1 pass can run -- in
+ *                practice give an arena of snlm_workspace_bytes per job)
+ * Returns SNLM_OK and *ctx, SNLM_EINVAL for a NULL ctx or a bad device,
+ * SNLM_EDEVICE if the HIP runtime fails. */
+int snlm_create(snlm_ctx **ctx, int device, void *stream, void *arena, size_t arena_bytes);
+
+/* Waits for all work of the context (including served jobs), stops the
+ * serving thread and releases library-owned resources.  Never frees caller
+ * memory.  NULL is accepted. */
+int snlm_destroy(snlm_ctx *ctx);
+
+/* Arena bytes one job needs for its FP32 intermediate image (synchronous
+ * calls), rounded up to 256 bytes. */
+size_t snlm_workspace_bytes(int H, int W, snlm_dtype dtype);
+
+/* Arena bytes one served job needs: staged input, intermediate, output. */
+size_t snlm_serving_bytes(int H, int W, snlm_dtype dtype);
+
+/* Separable NLM of one FP32 image with contiguous rows (ld = W).  Enqueued on
+ * the context stream; returns once enqueued.  Call snlm_sync for completion.
+ * Errors: SNLM_EINVAL (NULL pointers, H or W < 1, S or K out of range, h not
+ * > 0, unknown kernel/order, out overlapping img), SNLM_ENOMEM (arena smaller
+ * than snlm_workspace_bytes), SNLM_EDEVICE. */
+int snlm_denoise(snlm_ctx *ctx, const void *img, float *out, int H, int W, int S, int K,
+                 float h, int kernel, int order);
+
+/* As snlm_denoise with every option of snlm_job. */
+int snlm_denoise_ex(snlm_ctx *ctx, const snlm_job *job);
+
+/* Many images in one persistent launch per (S, K, kernel) class: each launch
+ * is captured once in a HIP graph (counter reset + persistent kernel) and
+ * replayed; its workgroups claim row tiles of every image, then column tiles,
+ * a column tile waiting only for the first-pass tiles of its own image.  The
+ * arena must hold the sum of the jobs' snlm_workspace_bytes.  Enqueued on the
+ * context stream.  Results are bitwise identical to snlm_denoise_ex of each
+ * job.  Errors as snlm_denoise_ex, plus SNLM_EINVAL for n < 1 and SNLM_ENOMEM
+ * when the jobs do not fit the arena together. */
+int snlm_denoise_batch(snlm_ctx *ctx, const snlm_job *jobs, int n);
+
+/* Waits for everything enqueued on the context stream by this library and
+ * reports device-side failures of batched launches (SNLM_EDEVICE). */
+int snlm_sync(snlm_ctx *ctx);
+
+/* Serving.  Submits a job to the context's scheduler and returns at once with
+ * a ticket.  The scheduler admits jobs in arrival order as arena space
+ * (snlm_serving_bytes per job) frees up, stages the image into the arena,
+ * runs admitted jobs in batched persistent launches that overlap on the
+ * device with launches already running, and copies each result to job->out.
+ * img and out must stay valid until snlm_poll returns non-PENDING.
+ * Errors: SNLM_EINVAL, SNLM_ENOMEM (the job can never fit the arena),
+ * SNLM_ECLOSED. */
+int snlm_submit(snlm_ctx *ctx, const snlm_job *job, uint64_t *ticket);
+
+/* SNLM_PENDING while the job runs; then its final status once (SNLM_OK or an
+ * error), after which the ticket is forgotten (SNLM_ENOTICKET). */
+int snlm_poll(snlm_ctx *ctx, uint64_t ticket);
+
+/* Timestamps of a finished served job, in microseconds of the host monotonic
+ * clock: submit, admission, completion observed.  SNLM_ENOTICKET if unknown.
+ * Must be called before the final snlm_poll of the ticket. */
+int snlm_job_times(snlm_ctx *ctx, uint64_t ticket, double *t_submit, double *t_admit,
+                   double *t_done);
+
+/* Host-side validation of a job (no device access).  SNLM_OK or SNLM_EINVAL,
+ * with the reason in *why (static string) when why is not NULL. */
+int snlm_validate(const snlm_job *job, const char **why);
+
+/* Selects the segment length for jobs of this shape class by timing
+ * candidates on the context stream with the given job (whose buffers are used
+ * as scratch input/output), and remembers it for later jobs with seg_len = 0
+ * of the same (S, K, kernel, size class).  *best receives the choice. */
+int snlm_autotune(snlm_ctx *ctx, const snlm_job *probe, int *best);
+
+/* Saves / loads the autotuner's choices as a small JSON file. */
+int snlm_autotune_save(snlm_ctx *ctx, const char *path);
+int snlm_autotune_load(snlm_ctx *ctx, const char *path);
+
+/* Segment length the library would use for this job (after validation). */
+int snlm_plan_seg_len(snlm_ctx *ctx, const snlm_job *job, int pass);
+
+/* Kernel timing for measurement.  enable = 1 clears and starts recording HIP
+ * events on the stream of each persistent batched launch (immediately around
+ * the graph replay: counter reset + persistent kernel) and of each direct
+ * pass launch; enable = 0 stops, waits for the recorded events and returns the
+ * summed device time of batched launches in *batch_ms (count in *batch_n) and
+ * of direct pass launches in *direct_ms (count in *direct_n).  Pointers may be
+ * NULL. */
+int snlm_timing(snlm_ctx *ctx, int enable, double *batch_ms, int *batch_n, double *direct_ms,
+                int *direct_n);
+
+const char *snlm_strerror(int status);
+const char *snlm_last_error(snlm_ctx *ctx);
+const char *snlm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SNLM_H */

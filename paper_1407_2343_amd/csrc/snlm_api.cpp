@@ -1,0 +1,1204 @@
+// Host side of libsnlm: argument checking, pass planning, direct launches,
+// batched persistent launches captured in HIP graphs, the autotuner and the
+// serving scheduler.  The C ABI is declared in include/snlm.h.
+#include "snlm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "snlm_registry.hpp"
+
+using snlm::BatchHeader;
+using snlm::BatchJob;
+using snlm::KernelArgs;
+using snlm::PassDesc;
+
+namespace snlm {
+// Clears the claim counter and the per-job counters of a batched launch (a
+// kernel rather than a memset, so that it can sit in a captured graph).
+__global__ void snlm_clear_counters(uint32_t* counters, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) counters[i] = 0u;
+}
+}  // namespace snlm
+
+namespace {
+
+constexpr int kChunk = snlm::kChunk;
+constexpr uint32_t kSpinLimit = 4000000u;  // bounds a dependency wait to a few seconds
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+double now_us() {
+    using namespace std::chrono;
+    return duration_cast<duration<double, std::micro>>(steady_clock::now().time_since_epoch())
+        .count();
+}
+
+// ---------------------------------------------------------------- registry --
+snlm::KernelRegistry g_reg;
+std::once_flag g_reg_once;
+
+void init_registry() {
+    std::call_once(g_reg_once, [] {
+        std::memset(&g_reg, 0, sizeof(g_reg));
+        snlm_register_s0(&g_reg);
+        snlm_register_s1(&g_reg);
+        snlm_register_s2(&g_reg);
+        snlm_register_s3(&g_reg);
+        snlm_register_s4(&g_reg);
+        snlm_register_s5(&g_reg);
+        snlm_register_s6(&g_reg);
+        snlm_register_s7(&g_reg);
+        snlm_register_s8(&g_reg);
+        snlm_register_s9(&g_reg);
+        snlm_register_s10(&g_reg);
+        snlm_register_s11(&g_reg);
+        snlm_register_s12(&g_reg);
+        snlm_register_s13(&g_reg);
+        snlm_register_s14(&g_reg);
+        snlm_register_s15(&g_reg);
+        snlm_register_s16(&g_reg);
+    });
+}
+
+int variant_of(const snlm_job& j) {
+    if (j.kernel == SNLM_GAUSS) return snlm::kVarGauss;
+    return j.sum == SNLM_SUM_KAHAN ? snlm::kVarBoxKahan : snlm::kVarBox;
+}
+
+bool pass_rows(const snlm_job& j, int pass) { return (pass == 0) == (j.order == SNLM_ROW_COL); }
+
+// Kernel of one pass of a job (the row-pass variant when its lines are rows).
+const void* kernel_fn(const snlm_job& j, int pass) {
+    init_registry();
+    return g_reg.fn[j.S][j.K][variant_of(j)][pass_rows(j, pass) ? 1 : 0];
+}
+
+// Batched launches group jobs whose passes use the same two kernels.
+struct ClassKey {
+    int S, K, var, order;
+    bool operator<(const ClassKey& o) const {
+        return std::tie(S, K, var, order) < std::tie(o.S, o.K, o.var, o.order);
+    }
+};
+ClassKey class_of(const snlm_job& j) { return ClassKey{j.S, j.K, variant_of(j), (int)j.order}; }
+
+// ---------------------------------------------------------------- checking --
+const char* check_job(const snlm_job* j) {
+    if (!j) return "job is NULL";
+    if (!j->img || !j->out) return "img and out must be non-NULL device pointers";
+    if (j->H < 1 || j->W < 1) return "H and W must be >= 1";
+    if (j->ld_in < j->W || j->ld_out < j->W) return "row pitches must be >= W";
+    if (j->dtype != SNLM_F32 && j->dtype != SNLM_F16) return "unknown dtype";
+    if (j->S < 0 || j->S > SNLM_MAX_S) return "S out of range [0, 16]";
+    if (j->K < 0 || j->K > SNLM_MAX_K) return "K out of range [0, 8]";
+    if (!(j->h > 0.0f)) return "h must be > 0 (NaN rejected)";
+    if (j->kernel != SNLM_BOX && j->kernel != SNLM_GAUSS) return "unknown kernel";
+    if (j->order != SNLM_ROW_COL && j->order != SNLM_COL_ROW) return "unknown order";
+    if (j->sum != SNLM_SUM_BLOCK && j->sum != SNLM_SUM_KAHAN && j->sum != SNLM_SUM_PLAIN)
+        return "unknown sum mode";
+    if (j->seg_len < 0 || j->seg_len % kChunk != 0) return "seg_len must be 0 or a multiple of 16";
+    if (std::isnan(j->beta)) return "beta is NaN";
+    const size_t esz = j->dtype == SNLM_F16 ? 2 : 4;
+    const double in_bytes = ((double)(j->H - 1) * j->ld_in + j->W) * esz;
+    const double out_bytes = ((double)(j->H - 1) * j->ld_out + j->W) * 4.0;
+    const double mid_bytes = (double)j->H * ((j->W + 15) / 16 * 16) * 4.0;
+    if (in_bytes >= 2147483647.0 || out_bytes >= 2147483647.0 || mid_bytes >= 2147483647.0)
+        return "image larger than 2 GiB";
+    const char* ib = (const char*)j->img;
+    const char* ob = (const char*)j->out;
+    if (ob < ib + (size_t)in_bytes && ib < ob + (size_t)out_bytes) return "out overlaps img";
+    return nullptr;
+}
+
+// The FP32 intermediate image has its row pitch padded to 16 floats, so that
+// row starts are 64-byte aligned for the vector loads and stores of the row pass.
+int mid_pitch(int W) { return (W + 15) / 16 * 16; }
+size_t mid_bytes(int H, int W) { return align_up((size_t)H * (size_t)mid_pitch(W) * 4, kAlign); }
+
+// ---------------------------------------------------------------- planning --
+// Autotuner memory: (S, K, variant, pass-line-length class, line-count class) -> seg_len
+struct TuneKey {
+    int S, K, var, nclass, lclass;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(S, K, var, nclass, lclass) < std::tie(o.S, o.K, o.var, o.nclass, o.lclass);
+    }
+};
+
+int size_class(int v) {  // power-of-two bucket
+    int c = 0;
+    while ((1 << (c + 1)) <= v && c < 30) ++c;
+    return c;
+}
+
+// Default segment length: split lines just finely enough to give every SIMD
+// one wave (target_waves), since each segment pays for a pre-chunk and one
+// wave per SIMD already keeps the VALU busy as well as more do (measured).
+int heuristic_seg_len(int groups, int n, int target_waves) {
+    const int nchunks = (n + kChunk - 1) / kChunk;
+    int want = (target_waves + groups - 1) / groups;  // segments per line wanted
+    want = std::max(1, std::min(want, nchunks));
+    return (nchunks + want - 1) / want * kChunk;
+}
+
+void fill_pass(PassDesc& d, const snlm_job& j, int pass, void* mid, int seg_len) {
+    std::memset(&d, 0, sizeof(d));
+    const bool rows_first = j.order == SNLM_ROW_COL;
+    const bool rows = (pass == 0) ? rows_first : !rows_first;
+    const int H = j.H, W = j.W;
+    const int Wp = mid_pitch(W);
+    if (pass == 0) {
+        d.in = j.img;
+        d.in_f16 = j.dtype == SNLM_F16;
+        d.in_bytes = (uint32_t)(((size_t)(H - 1) * j.ld_in + W) * (j.dtype == SNLM_F16 ? 2 : 4));
+        d.in_line = rows ? j.ld_in : 1;
+        d.in_pos = rows ? 1 : j.ld_in;
+        d.out = (float*)mid;
+        d.out_bytes = (uint32_t)((size_t)H * Wp * 4);
+        d.out_line = rows ? Wp : 1;
+        d.out_pos = rows ? 1 : Wp;
+    } else {
+        d.in = mid;
+        d.in_f16 = 0;
+        d.in_bytes = (uint32_t)((size_t)H * Wp * 4);
+        d.in_line = rows ? Wp : 1;
+        d.in_pos = rows ? 1 : Wp;
+        d.out = j.out;
+        d.out_bytes = (uint32_t)(((size_t)(H - 1) * j.ld_out + W) * 4);
+        d.out_line = rows ? j.ld_out : 1;
+        d.out_pos = rows ? 1 : j.ld_out;
+    }
+    d.nlines = rows ? H : W;
+    d.n = rows ? W : H;
+    const bool whole_line = j.kernel == SNLM_BOX && j.sum != SNLM_SUM_BLOCK;
+    d.restart = (j.kernel == SNLM_BOX && j.sum == SNLM_SUM_BLOCK) ? 1 : 0;
+    const int full = (d.n + kChunk - 1) / kChunk * kChunk;
+    if (whole_line)
+        seg_len = full;  // running sums over the whole line: one segment
+    else
+        seg_len = std::min(std::max(seg_len, kChunk), full);
+    d.seg_len = seg_len;
+    d.nseg = (d.n + seg_len - 1) / seg_len;
+    d.ngroups = (d.nlines + snlm::kLanes - 1) / snlm::kLanes;
+    // Lift scale: exp2(-(a dx)^2) = exp(-dx^2 / h^2) with a = sqrt(log2 e) / h.
+    // h = inf uses a = 2^-64: scaling by a power of two is exact, and every
+    // weight exp2(-(a dx)^2) then rounds to 1 for |dx| < 2^40.
+    double a = std::isinf(j.h) ? std::ldexp(1.0, -64) : std::sqrt(1.4426950408889634) / (double)j.h;
+    a = std::min(a, 1099511627776.0);  // 2^40: keeps (a x)^2 sums finite for |x| < 2^20
+    d.alpha = (float)a;
+    d.inv_alpha = (float)(1.0 / (double)d.alpha);
+    const double beta = (j.beta > 0.0f) ? (double)j.beta : j.K / 2.0;
+    for (int k = 0; k <= snlm::kMaxK; ++k) {
+        double g = 1.0;
+        if (j.kernel == SNLM_GAUSS && k > 0 && k <= j.K) g = std::exp(-(double)k * k / (2.0 * beta * beta));
+        d.taps[k] = (float)g;
+    }
+}
+
+// ---------------------------------------------------------------- context --
+struct Region {
+    size_t off, len;
+};
+
+// First-fit allocator over the caller's arena.
+class ArenaAlloc {
+   public:
+    void reset(size_t cap) {
+        cap_ = cap;
+        free_.clear();
+        if (cap) free_.push_back({0, cap});
+        used_ = high_ = 0;
+    }
+    bool alloc(size_t len, size_t* off) {
+        len = align_up(len, kAlign);
+        for (size_t i = 0; i < free_.size(); ++i) {
+            if (free_[i].len >= len) {
+                *off = free_[i].off;
+                free_[i].off += len;
+                free_[i].len -= len;
+                if (free_[i].len == 0) free_.erase(free_.begin() + i);
+                used_ += len;
+                high_ = std::max(high_, used_);
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t len) {
+        len = align_up(len, kAlign);
+        used_ -= len;
+        free_.push_back({off, len});
+        std::sort(free_.begin(), free_.end(), [](const Region& a, const Region& b) { return a.off < b.off; });
+        std::vector<Region> merged;
+        for (auto& r : free_) {
+            if (!merged.empty() && merged.back().off + merged.back().len == r.off)
+                merged.back().len += r.len;
+            else
+                merged.push_back(r);
+        }
+        free_.swap(merged);
+    }
+    size_t cap() const { return cap_; }
+    size_t high() const { return high_; }
+
+   private:
+    size_t cap_ = 0, used_ = 0, high_ = 0;
+    std::vector<Region> free_;
+};
+
+// Device tables + counters for one persistent launch, with pinned staging.
+struct LaunchSlot {
+    char* d_tab = nullptr;
+    size_t d_cap = 0;
+    uint32_t* d_cnt = nullptr;
+    size_t cnt_cap = 0;
+    char* h_tab = nullptr;
+    size_t h_cap = 0;
+    hipEvent_t staged = nullptr;  // host staging buffer free again
+    const void* fn = nullptr;     // first-pass kernel of the uploaded class
+    const void* fn2 = nullptr;    // second-pass kernel
+    const void* fn_rows = nullptr;  // row-pass variant (handles both passes; fused mode)
+    int njobs = 0, ntiles = 0, ntiles_first = 0;
+    size_t off_jobs = 0, off_tiles = 0;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    const void* g_fn = nullptr;
+    const void* g_fn2 = nullptr;
+    int g_grid = 0, g_grid2 = 0, g_lo2 = 0, g_hi = 0, g_njobs = 0;
+    bool g_split = false;
+    char* g_tab = nullptr;
+    uint32_t* g_cnt = nullptr;
+    int g_ncnt = 0;
+};
+
+struct ServeJob {
+    uint64_t ticket;
+    snlm_job job;
+    size_t need;
+    size_t off = 0;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    int status = SNLM_PENDING;
+};
+
+struct InFlight {
+    std::vector<std::shared_ptr<ServeJob>> jobs;
+    hipEvent_t done = nullptr;
+    int slot_base = 0;
+    int nslots = 0;
+    int stream = 0;
+};
+
+}  // namespace
+
+struct snlm_ctx {
+    int device = 0;
+    hipStream_t user = nullptr;
+    hipStream_t work = nullptr;
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    int num_cu = 0;
+    std::string last_error;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    uint32_t* d_status = nullptr;  // device-side failure flags of batched launches
+    std::vector<LaunchSlot> slots;
+    std::map<TuneKey, int> tuned;
+    std::mutex tune_mu;
+    int tune_epoch = 0;  // bumped whenever tuned changes (invalidates cached batch plans)
+    // Batched launches: split (default) runs all first-pass tiles, then all
+    // second-pass tiles, as two persistent launches in one graph; fused
+    // (SNLM_BATCH_MODE=fused) runs one launch whose second-pass tiles wait on
+    // per-image counters.
+    bool batch_split = true;
+    uint64_t last_batch_hash = 0;
+    int last_batch_classes = 0;
+
+    // measurement: event pairs around batched graph replays / direct launches
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> t_batch, t_direct, t_pool;
+
+    // serving
+    std::mutex mu;
+    std::condition_variable cv;
+    std::thread sched;
+    bool sched_started = false;
+    bool closing = false;
+    uint64_t next_ticket = 1;
+    std::deque<std::shared_ptr<ServeJob>> pending;
+    std::map<uint64_t, std::shared_ptr<ServeJob>> jobs;
+    ArenaAlloc alloc;
+    std::vector<hipStream_t> serve_streams;
+    std::vector<LaunchSlot> serve_slots;
+    std::vector<uint32_t*> serve_status;
+    std::vector<uint32_t*> h_serve_status;
+};
+
+namespace {
+
+int fail(snlm_ctx* c, int code, const std::string& msg) {
+    if (c) c->last_error = msg;
+    return code;
+}
+
+int hip_fail(snlm_ctx* c, hipError_t e, const char* what) {
+    return fail(c, SNLM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_CHECK(ctx, expr)                                  \
+    do {                                                      \
+        hipError_t e_ = (expr);                               \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+    } while (0)
+
+int occupancy_grid(snlm_ctx* c, const void* fn) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, snlm::kLanes, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 4;
+    return per_cu * c->num_cu;
+}
+
+// Segment length of a pass.  shared_groups is the number of 64-line groups
+// of every image in the same launch (0: this image alone), so that a batch
+// splits its lines only as finely as the whole launch needs.
+int chosen_seg_len(snlm_ctx* c, const snlm_job& j, int pass, int shared_groups = 0) {
+    if (j.seg_len > 0) return j.seg_len;
+    const bool rows_first = j.order == SNLM_ROW_COL;
+    const bool rows = (pass == 0) ? rows_first : !rows_first;
+    const int n = rows ? j.W : j.H;
+    const int nlines = rows ? j.H : j.W;
+    {
+        std::lock_guard<std::mutex> g(c->tune_mu);
+        auto it = c->tuned.find(TuneKey{j.S, j.K, variant_of(j), size_class(n), size_class(nlines)});
+        if (it != c->tuned.end()) return it->second;
+    }
+    const int target = 4 * std::max(c->num_cu, 1);  // one wave per SIMD
+    const int groups = shared_groups > 0 ? shared_groups : (nlines + snlm::kLanes - 1) / snlm::kLanes;
+    return heuristic_seg_len(groups, n, target);
+}
+
+int groups_of(const snlm_job& j, int pass) {
+    const bool rows = (pass == 0) == (j.order == SNLM_ROW_COL);
+    const int nlines = rows ? j.H : j.W;
+    return (nlines + snlm::kLanes - 1) / snlm::kLanes;
+}
+
+int timing_pair(snlm_ctx* c, std::pair<hipEvent_t, hipEvent_t>* p) {
+    if (!c->t_pool.empty()) {
+        *p = c->t_pool.back();
+        c->t_pool.pop_back();
+        return SNLM_OK;
+    }
+    HIP_CHECK(c, hipEventCreate(&p->first));
+    HIP_CHECK(c, hipEventCreate(&p->second));
+    return SNLM_OK;
+}
+
+int launch_direct(snlm_ctx* c, const void* fn, const PassDesc& d, hipStream_t st,
+                  bool timed = true) {
+    KernelArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.direct = d;
+    void* args[] = {&a};
+    const int grid = d.ngroups * d.nseg;
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    const bool t = timed && c->timing;
+    if (t) {
+        int rc = timing_pair(c, &ev);
+        if (rc) return rc;
+        HIP_CHECK(c, hipEventRecord(ev.first, st));
+    }
+    HIP_CHECK(c, hipLaunchKernel(fn, dim3(grid), dim3(snlm::kLanes), args, 0, st));
+    if (t) {
+        HIP_CHECK(c, hipEventRecord(ev.second, st));
+        c->t_direct.push_back(ev);
+    }
+    return SNLM_OK;
+}
+
+int enqueue_job(snlm_ctx* c, const snlm_job& j, void* mid, hipStream_t st) {
+    for (int pass = 0; pass < 2; ++pass) {
+        const void* fn = kernel_fn(j, pass);
+        if (!fn) return fail(c, SNLM_EDEVICE, "kernel variant not compiled");
+        PassDesc d;
+        fill_pass(d, j, pass, mid, chosen_seg_len(c, j, pass));
+        int rc = launch_direct(c, fn, d, st);
+        if (rc) return rc;
+    }
+    return SNLM_OK;
+}
+
+// Order the library's work stream after the caller's stream.
+int fence_in(snlm_ctx* c, hipStream_t target) {
+    HIP_CHECK(c, hipEventRecord(c->ev_in, c->user));
+    HIP_CHECK(c, hipStreamWaitEvent(target, c->ev_in, 0));
+    return SNLM_OK;
+}
+int fence_out(snlm_ctx* c, hipStream_t from) {
+    HIP_CHECK(c, hipEventRecord(c->ev_out, from));
+    HIP_CHECK(c, hipStreamWaitEvent(c->user, c->ev_out, 0));
+    return SNLM_OK;
+}
+
+// ---------------------------------------------------------------- batches --
+struct ClassPlan {
+    const void* fn[2] = {nullptr, nullptr};  // first-pass and second-pass kernels
+    std::vector<BatchJob> jobs;
+    std::vector<uint32_t> tile_job;
+    int ntiles_first = 0;
+};
+
+// Groups jobs by kernel variant and lays out their tiles: every first-pass
+// tile of the class, then every second-pass tile, both in job order.
+void plan_classes(snlm_ctx* c, const std::vector<const snlm_job*>& jobs,
+                  const std::vector<char*>& mids, std::vector<ClassPlan>& out) {
+    std::map<ClassKey, size_t> idx;
+    std::map<ClassKey, int> groups[2];
+    for (size_t i = 0; i < jobs.size(); ++i)
+        for (int p = 0; p < 2; ++p) groups[p][class_of(*jobs[i])] += groups_of(*jobs[i], p);
+    for (size_t i = 0; i < jobs.size(); ++i) {
+        const ClassKey fn = class_of(*jobs[i]);
+        auto it = idx.find(fn);
+        if (it == idx.end()) {
+            idx[fn] = out.size();
+            out.emplace_back();
+            out.back().fn[0] = kernel_fn(*jobs[i], 0);
+            out.back().fn[1] = kernel_fn(*jobs[i], 1);
+            it = idx.find(fn);
+        }
+        ClassPlan& cp = out[it->second];
+        BatchJob bj;
+        std::memset(&bj, 0, sizeof(bj));
+        for (int p = 0; p < 2; ++p) {
+            fill_pass(bj.pass[p], *jobs[i], p, mids[i], chosen_seg_len(c, *jobs[i], p, groups[p][fn]));
+            bj.tiles[p] = bj.pass[p].ngroups * bj.pass[p].nseg;
+        }
+        cp.jobs.push_back(bj);
+    }
+    for (auto& cp : out) {
+        int t = 0;
+        for (size_t j = 0; j < cp.jobs.size(); ++j) {
+            cp.jobs[j].tile_base[0] = t;
+            for (int k = 0; k < cp.jobs[j].tiles[0]; ++k) cp.tile_job.push_back((uint32_t)j);
+            t += cp.jobs[j].tiles[0];
+        }
+        cp.ntiles_first = t;
+        for (size_t j = 0; j < cp.jobs.size(); ++j) {
+            cp.jobs[j].tile_base[1] = t;
+            for (int k = 0; k < cp.jobs[j].tiles[1]; ++k) cp.tile_job.push_back((uint32_t)j);
+            t += cp.jobs[j].tiles[1];
+        }
+    }
+}
+
+int ensure_slot(snlm_ctx* c, LaunchSlot& s, size_t tab_bytes, size_t ncnt) {
+    if (s.staged == nullptr) HIP_CHECK(c, hipEventCreateWithFlags(&s.staged, hipEventDisableTiming));
+    if (s.d_cap < tab_bytes) {
+        if (s.d_tab) HIP_CHECK(c, hipFree(s.d_tab));
+        s.d_tab = nullptr;
+        size_t cap = align_up(std::max(tab_bytes, (size_t)1 << 16) * 2, kAlign);
+        HIP_CHECK(c, hipMalloc(&s.d_tab, cap));
+        s.d_cap = cap;
+    }
+    if (s.h_cap < tab_bytes) {
+        HIP_CHECK(c, hipEventSynchronize(s.staged));
+        if (s.h_tab) HIP_CHECK(c, hipHostFree(s.h_tab));
+        s.h_tab = nullptr;
+        size_t cap = align_up(std::max(tab_bytes, (size_t)1 << 16) * 2, kAlign);
+        HIP_CHECK(c, hipHostMalloc(&s.h_tab, cap, hipHostMallocDefault));
+        s.h_cap = cap;
+    }
+    if (s.cnt_cap < ncnt) {
+        if (s.d_cnt) HIP_CHECK(c, hipFree(s.d_cnt));
+        s.d_cnt = nullptr;
+        size_t cap = std::max(ncnt * 2, (size_t)1024);
+        HIP_CHECK(c, hipMalloc(&s.d_cnt, cap * sizeof(uint32_t)));
+        s.cnt_cap = cap;
+    }
+    return SNLM_OK;
+}
+
+const void* pass_rows_fn(const ClassPlan& cp) {
+    // fn[p] is the row variant for the pass whose lines are rows
+    init_registry();
+    for (int S = 0; S <= snlm::kMaxS; ++S)
+        for (int K = 0; K <= snlm::kMaxK; ++K)
+            for (int v = 0; v < snlm::kNumVariants; ++v)
+                for (int r = 0; r < 2; ++r)
+                    if (g_reg.fn[S][K][v][r] == cp.fn[0]) return g_reg.fn[S][K][v][1];
+    return cp.fn[0];
+}
+
+// Uploads one class's tables into a slot (stream-ordered on st).
+int upload_class(snlm_ctx* c, LaunchSlot& s, const ClassPlan& cp, hipStream_t st) {
+    const size_t off_jobs = align_up(sizeof(BatchHeader), 64);
+    const size_t off_tiles = align_up(off_jobs + cp.jobs.size() * sizeof(BatchJob), 64);
+    const size_t tab_bytes = off_tiles + cp.tile_job.size() * sizeof(uint32_t);
+    const size_t ncnt = 2 + cp.jobs.size();
+    int rc = ensure_slot(c, s, tab_bytes, ncnt);
+    if (rc) return rc;
+    HIP_CHECK(c, hipEventSynchronize(s.staged));  // previous upload from h_tab finished
+    BatchHeader hdr;
+    hdr.njobs = (int)cp.jobs.size();
+    hdr.ntiles_first = cp.ntiles_first;
+    hdr.ntiles = (int)cp.tile_job.size();
+    hdr.spin_limit = kSpinLimit;
+    std::memcpy(s.h_tab, &hdr, sizeof(hdr));
+    std::memcpy(s.h_tab + off_jobs, cp.jobs.data(), cp.jobs.size() * sizeof(BatchJob));
+    std::memcpy(s.h_tab + off_tiles, cp.tile_job.data(), cp.tile_job.size() * sizeof(uint32_t));
+    HIP_CHECK(c, hipMemcpyAsync(s.d_tab, s.h_tab, tab_bytes, hipMemcpyHostToDevice, st));
+    HIP_CHECK(c, hipEventRecord(s.staged, st));
+    s.fn = cp.fn[0];
+    s.fn2 = cp.fn[1];
+    // the row-pass variant also handles column passes (fused launches)
+    s.fn_rows = pass_rows_fn(cp);
+    s.njobs = hdr.njobs;
+    s.ntiles = hdr.ntiles;
+    s.ntiles_first = hdr.ntiles_first;
+    s.off_jobs = off_jobs;
+    s.off_tiles = off_tiles;
+    return SNLM_OK;
+}
+
+// Enqueues the persistent launch(es) of the class last uploaded into the
+// slot, as a replay of a captured graph (graphed = true) or as plain launches.
+// fused: one launch over all tiles, second-pass tiles waiting on per-image
+// counters; split: a launch over the first-pass tiles, then one over the rest.
+int launch_class(snlm_ctx* c, LaunchSlot& s, hipStream_t st, uint32_t* d_status, bool graphed) {
+    const bool split = c->batch_split;
+    KernelArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.hdr = (const BatchHeader*)s.d_tab;
+    a.jobs = (const BatchJob*)(s.d_tab + s.off_jobs);
+    a.tile_job = (const uint32_t*)(s.d_tab + s.off_tiles);
+    a.counters = s.d_cnt;
+    a.status = d_status;
+    KernelArgs a2 = a;
+    int grid1, grid2 = 0;
+    const void* f1 = split ? s.fn : s.fn_rows;
+    const void* f2 = s.fn2;
+    const int cap = occupancy_grid(c, f1);
+    const int cap2 = occupancy_grid(c, f2);
+    if (!split) {
+        a.claim = s.d_cnt;
+        a.tile_lo = 0;
+        a.tile_hi = s.ntiles;
+        a.wait = 1;
+        grid1 = std::max(1, std::min(cap, s.ntiles));
+    } else {
+        a.claim = s.d_cnt;
+        a.tile_lo = 0;
+        a.tile_hi = s.ntiles_first;
+        a.wait = 0;
+        a2.claim = s.d_cnt + 1 + s.njobs;
+        a2.tile_lo = s.ntiles_first;
+        a2.tile_hi = s.ntiles;
+        a2.wait = 0;
+        grid1 = std::max(1, std::min(cap, s.ntiles_first));
+        grid2 = std::max(1, std::min(cap2, s.ntiles - s.ntiles_first));
+    }
+    auto enqueue = [&](int ncnt_clear) -> hipError_t {
+        const int gclear = (ncnt_clear + 255) / 256;
+        void* cargs[] = {(void*)&a.counters, (void*)&ncnt_clear};
+        hipError_t e = hipLaunchKernel((const void*)&snlm::snlm_clear_counters, dim3(gclear),
+                                       dim3(256), cargs, 0, st);
+        if (e != hipSuccess) return e;
+        void* k1[] = {&a};
+        e = hipLaunchKernel(f1, dim3(grid1), dim3(snlm::kLanes), k1, 0, st);
+        if (e != hipSuccess || !split) return e;
+        void* k2[] = {&a2};
+        return hipLaunchKernel(f2, dim3(grid2), dim3(snlm::kLanes), k2, 0, st);
+    };
+    if (!graphed) {
+        hipError_t e = enqueue(2 + s.njobs);
+        if (e != hipSuccess) return hip_fail(c, e, "batched launch");
+        return SNLM_OK;
+    }
+    // The graph depends only on the kernel, the grids and the table/counter
+    // buffers; the batch composition lives in the uploaded table.
+    const int graph_ncnt = (int)s.cnt_cap;
+    if (!(s.exec && s.g_fn == f1 && s.g_fn2 == f2 && s.g_grid == grid1 && s.g_grid2 == grid2 &&
+          s.g_tab == s.d_tab && s.g_cnt == s.d_cnt && s.g_ncnt == graph_ncnt &&
+          s.g_split == split && s.g_lo2 == s.ntiles_first && s.g_hi == s.ntiles &&
+          s.g_njobs == s.njobs)) {
+        if (s.exec) {
+            HIP_CHECK(c, hipGraphExecDestroy(s.exec));
+            s.exec = nullptr;
+        }
+        if (s.graph) {
+            HIP_CHECK(c, hipGraphDestroy(s.graph));
+            s.graph = nullptr;
+        }
+        HIP_CHECK(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        hipError_t e1 = enqueue(graph_ncnt);
+        hipGraph_t g = nullptr;
+        hipError_t e3 = hipStreamEndCapture(st, &g);
+        if (e1 != hipSuccess) return hip_fail(c, e1, "capture of the batched launch");
+        if (e3 != hipSuccess) return hip_fail(c, e3, "hipStreamEndCapture");
+        s.graph = g;
+        HIP_CHECK(c, hipGraphInstantiate(&s.exec, g, nullptr, nullptr, 0));
+        s.g_fn = f1;
+        s.g_fn2 = f2;
+        s.g_grid = grid1;
+        s.g_grid2 = grid2;
+        s.g_tab = s.d_tab;
+        s.g_cnt = s.d_cnt;
+        s.g_ncnt = graph_ncnt;
+        s.g_split = split;
+        s.g_lo2 = s.ntiles_first;
+        s.g_hi = s.ntiles;
+        s.g_njobs = s.njobs;
+    }
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    if (c->timing) {
+        int rc2 = timing_pair(c, &ev);
+        if (rc2) return rc2;
+        HIP_CHECK(c, hipEventRecord(ev.first, st));
+    }
+    HIP_CHECK(c, hipGraphLaunch(s.exec, st));
+    if (c->timing) {
+        HIP_CHECK(c, hipEventRecord(ev.second, st));
+        c->t_batch.push_back(ev);
+    }
+    return SNLM_OK;
+}
+
+void free_slot(LaunchSlot& s) {
+    if (s.exec) (void)hipGraphExecDestroy(s.exec);
+    if (s.graph) (void)hipGraphDestroy(s.graph);
+    if (s.d_tab) (void)hipFree(s.d_tab);
+    if (s.d_cnt) (void)hipFree(s.d_cnt);
+    if (s.staged) {
+        (void)hipEventSynchronize(s.staged);
+        (void)hipEventDestroy(s.staged);
+    }
+    if (s.h_tab) (void)hipHostFree(s.h_tab);
+    s = LaunchSlot();
+}
+
+// ---------------------------------------------------------------- serving --
+constexpr int kServeStreams = 3;  // launches that may overlap on the device
+
+void serve_loop(snlm_ctx* c);
+
+int start_scheduler(snlm_ctx* c) {
+    if (c->sched_started) return SNLM_OK;
+    HIP_CHECK(c, hipSetDevice(c->device));
+    c->serve_streams.resize(kServeStreams, nullptr);
+    c->serve_slots.resize(kServeStreams * 4);
+    c->serve_status.resize(kServeStreams, nullptr);
+    c->h_serve_status.resize(kServeStreams, nullptr);
+    for (int i = 0; i < kServeStreams; ++i) {
+        HIP_CHECK(c, hipStreamCreateWithFlags(&c->serve_streams[i], hipStreamNonBlocking));
+        HIP_CHECK(c, hipMalloc(&c->serve_status[i], sizeof(uint32_t)));
+        HIP_CHECK(c, hipMemset(c->serve_status[i], 0, sizeof(uint32_t)));
+        HIP_CHECK(c, hipHostMalloc(&c->h_serve_status[i], sizeof(uint32_t), hipHostMallocDefault));
+    }
+    c->alloc.reset(c->arena_bytes);
+    c->sched = std::thread(serve_loop, c);
+    c->sched_started = true;
+    return SNLM_OK;
+}
+
+// Launches every admitted job as one round: per kernel class, one persistent
+// launch on stream `si`, its tables in slots [4*si, 4*si+4) (more classes
+// than that wait for the next round).
+int launch_round(snlm_ctx* c, std::vector<std::shared_ptr<ServeJob>>& round, int si,
+                 InFlight& fl) {
+    hipStream_t st = c->serve_streams[si];
+    std::vector<const snlm_job*> js;
+    std::vector<char*> mids;
+    for (auto& sj : round) {
+        js.push_back(&sj->job);
+        mids.push_back(c->arena + sj->off);
+    }
+    std::vector<ClassPlan> plans;
+    plan_classes(c, js, mids, plans);
+    if (plans.size() > 4) return fail(c, SNLM_EINVAL, "too many classes in one round");
+    for (size_t k = 0; k < plans.size(); ++k) {
+        LaunchSlot& sl = c->serve_slots[si * 4 + k];
+        int rc = upload_class(c, sl, plans[k], st);
+        if (!rc) rc = launch_class(c, sl, st, c->serve_status[si], false);
+        if (rc) return rc;
+    }
+    HIP_CHECK(c, hipMemcpyAsync(c->h_serve_status[si], c->serve_status[si], sizeof(uint32_t),
+                                hipMemcpyDeviceToHost, st));
+    if (!fl.done) HIP_CHECK(c, hipEventCreateWithFlags(&fl.done, hipEventDisableTiming));
+    HIP_CHECK(c, hipEventRecord(fl.done, st));
+    fl.stream = si;
+    return SNLM_OK;
+}
+
+void serve_loop(snlm_ctx* c) {
+    (void)hipSetDevice(c->device);
+    std::vector<InFlight> flights(kServeStreams);
+    std::vector<bool> busy(kServeStreams, false);
+    for (;;) {
+        std::vector<std::shared_ptr<ServeJob>> round;
+        int free_stream = -1;
+        {
+            std::unique_lock<std::mutex> lk(c->mu);
+            // retire finished launches
+            for (int i = 0; i < kServeStreams; ++i) {
+                if (!busy[i]) continue;
+                hipError_t q = hipEventQuery(flights[i].done);
+                if (q == hipErrorNotReady) continue;
+                const double t = now_us();
+                const bool dev_fail = (q != hipSuccess) || *c->h_serve_status[i] != 0;
+                for (auto& sj : flights[i].jobs) {
+                    sj->status = dev_fail ? SNLM_EDEVICE : SNLM_OK;
+                    sj->t_done = t;
+                    c->alloc.release(sj->off, sj->need);
+                }
+                if (dev_fail) {
+                    c->last_error = "served launch failed on the device";
+                    *c->h_serve_status[i] = 0;
+                    (void)hipMemset(c->serve_status[i], 0, sizeof(uint32_t));
+                }
+                flights[i].jobs.clear();
+                busy[i] = false;
+            }
+            // admit in arrival order while the arena has room
+            const double t = now_us();
+            std::vector<std::shared_ptr<ServeJob>> admitted;
+            for (int i = 0; i < kServeStreams; ++i)
+                if (!busy[i]) {
+                    free_stream = i;
+                    break;
+                }
+            if (free_stream >= 0) {
+                std::map<ClassKey, int> classes;
+                while (!c->pending.empty()) {
+                    auto& sj = c->pending.front();
+                    const ClassKey fn = class_of(sj->job);
+                    if (!classes.count(fn) && classes.size() >= 4) break;
+                    size_t off;
+                    if (!c->alloc.alloc(sj->need, &off)) break;
+                    sj->off = off;
+                    sj->t_admit = t;
+                    classes[fn] = 1;
+                    round.push_back(sj);
+                    c->pending.pop_front();
+                }
+            }
+            bool any_busy = false;
+            for (int i = 0; i < kServeStreams; ++i) any_busy = any_busy || busy[i];
+            if (round.empty()) {
+                if (c->closing && c->pending.empty() && !any_busy) return;
+                if (any_busy)
+                    c->cv.wait_for(lk, std::chrono::microseconds(20));
+                else
+                    c->cv.wait_for(lk, std::chrono::milliseconds(2));
+                continue;
+            }
+        }
+        InFlight& fl = flights[free_stream];
+        int rc = launch_round(c, round, free_stream, fl);
+        std::lock_guard<std::mutex> lk(c->mu);
+        if (rc != SNLM_OK) {
+            const double t = now_us();
+            for (auto& sj : round) {
+                sj->status = rc;
+                sj->t_done = t;
+                c->alloc.release(sj->off, sj->need);
+            }
+            continue;
+        }
+        fl.jobs = round;
+        busy[free_stream] = true;
+    }
+}
+
+}  // namespace
+
+// ================================================================= C ABI ===
+extern "C" {
+
+const char* snlm_version(void) { return "snlm 0.1 (gfx950)"; }
+
+const char* snlm_strerror(int s) {
+    switch (s) {
+        case SNLM_OK: return "ok";
+        case SNLM_PENDING: return "pending";
+        case SNLM_EINVAL: return "invalid argument";
+        case SNLM_ENOMEM: return "does not fit the arena or table capacity";
+        case SNLM_EDEVICE: return "device or HIP runtime error";
+        case SNLM_ENOTICKET: return "unknown ticket";
+        case SNLM_ECLOSED: return "context is closing";
+        default: return "unknown status";
+    }
+}
+
+const char* snlm_last_error(snlm_ctx* c) { return c ? c->last_error.c_str() : "no context"; }
+
+int snlm_validate(const snlm_job* j, const char** why) {
+    const char* w = check_job(j);
+    if (why) *why = w ? w : "ok";
+    return w ? SNLM_EINVAL : SNLM_OK;
+}
+
+size_t snlm_workspace_bytes(int H, int W, snlm_dtype dtype) {
+    (void)dtype;
+    if (H < 1 || W < 1) return 0;
+    return mid_bytes(H, W);
+}
+
+size_t snlm_serving_bytes(int H, int W, snlm_dtype dtype) { return snlm_workspace_bytes(H, W, dtype); }
+
+int snlm_create(snlm_ctx** out, int device, void* stream, void* arena, size_t arena_bytes) {
+    if (!out) return SNLM_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SNLM_EINVAL;
+    if (!arena && arena_bytes) return SNLM_EINVAL;
+    init_registry();
+    std::unique_ptr<snlm_ctx> c(new snlm_ctx());
+    c->device = device;
+    c->user = (hipStream_t)stream;
+    c->arena = (char*)arena;
+    c->arena_bytes = arena_bytes;
+    if (hipSetDevice(device) != hipSuccess) return SNLM_EDEVICE;
+    if (hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        return SNLM_EDEVICE;
+    if (hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking) != hipSuccess) return SNLM_EDEVICE;
+    if (hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess) return SNLM_EDEVICE;
+    if (hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess) return SNLM_EDEVICE;
+    if (hipMalloc(&c->d_status, sizeof(uint32_t)) != hipSuccess) return SNLM_EDEVICE;
+    if (hipMemset(c->d_status, 0, sizeof(uint32_t)) != hipSuccess) return SNLM_EDEVICE;
+    if (hipDeviceSynchronize() != hipSuccess) return SNLM_EDEVICE;
+    c->alloc.reset(arena_bytes);
+    if (const char* m = std::getenv("SNLM_BATCH_MODE")) c->batch_split = std::strcmp(m, "fused") != 0;
+    *out = c.release();
+    return SNLM_OK;
+}
+
+int snlm_destroy(snlm_ctx* c) {
+    if (!c) return SNLM_OK;
+    (void)hipSetDevice(c->device);
+    if (c->sched_started) {
+        {
+            std::lock_guard<std::mutex> lk(c->mu);
+            c->closing = true;
+        }
+        c->cv.notify_all();
+        c->sched.join();
+    }
+    (void)hipStreamSynchronize(c->work);
+    for (auto& s : c->slots) free_slot(s);
+    for (auto& s : c->serve_slots) free_slot(s);
+    for (auto st : c->serve_streams)
+        if (st) (void)hipStreamDestroy(st);
+    for (auto p : c->serve_status)
+        if (p) (void)hipFree(p);
+    for (auto p : c->h_serve_status)
+        if (p) (void)hipHostFree(p);
+    for (auto* l : {&c->t_batch, &c->t_direct, &c->t_pool})
+        for (auto& ev : *l) {
+            (void)hipEventDestroy(ev.first);
+            (void)hipEventDestroy(ev.second);
+        }
+    if (c->d_status) (void)hipFree(c->d_status);
+    if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+    if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+    if (c->work) (void)hipStreamDestroy(c->work);
+    delete c;
+    return SNLM_OK;
+}
+
+int snlm_denoise_ex(snlm_ctx* c, const snlm_job* j) {
+    if (!c) return SNLM_EINVAL;
+    const char* why = check_job(j);
+    if (why) return fail(c, SNLM_EINVAL, why);
+    if (mid_bytes(j->H, j->W) > c->arena_bytes)
+        return fail(c, SNLM_ENOMEM, "arena smaller than snlm_workspace_bytes(H, W)");
+    HIP_CHECK(c, hipSetDevice(c->device));
+    return enqueue_job(c, *j, c->arena, c->user);
+}
+
+int snlm_denoise(snlm_ctx* c, const void* img, float* out, int H, int W, int S, int K, float h,
+                 int kernel, int order) {
+    snlm_job j;
+    std::memset(&j, 0, sizeof(j));
+    j.img = img;
+    j.out = out;
+    j.H = H;
+    j.W = W;
+    j.ld_in = W;
+    j.ld_out = W;
+    j.dtype = SNLM_F32;
+    j.S = S;
+    j.K = K;
+    j.h = h;
+    j.beta = 0.0f;
+    j.kernel = (snlm_kernel)kernel;
+    j.order = (snlm_order)order;
+    j.sum = SNLM_SUM_BLOCK;
+    j.seg_len = 0;
+    return snlm_denoise_ex(c, &j);
+}
+
+int snlm_denoise_batch(snlm_ctx* c, const snlm_job* jobs, int n) {
+    if (!c) return SNLM_EINVAL;
+    if (!jobs || n < 1) return fail(c, SNLM_EINVAL, "need at least one job");
+    // An identical batch (same jobs, same arena, same tuning) reuses the tables
+    // already on the device and only replays the graphs.
+    uint64_t hash = 1469598103934665603ull;
+    auto mix = [&hash](const void* p, size_t len) {
+        const unsigned char* b = (const unsigned char*)p;
+        for (size_t i = 0; i < len; ++i) hash = (hash ^ b[i]) * 1099511628211ull;
+    };
+    mix(jobs, sizeof(snlm_job) * (size_t)n);
+    mix(&c->arena, sizeof(c->arena));
+    mix(&c->tune_epoch, sizeof(c->tune_epoch));
+    if (c->last_batch_classes > 0 && hash == c->last_batch_hash) {
+        HIP_CHECK(c, hipSetDevice(c->device));
+        int rc = fence_in(c, c->work);
+        if (rc) return rc;
+        for (int k = 0; k < c->last_batch_classes; ++k) {
+            rc = launch_class(c, c->slots[k], c->work, c->d_status, true);
+            if (rc) return rc;
+        }
+        return fence_out(c, c->work);
+    }
+    c->last_batch_classes = 0;
+    size_t need = 0;
+    std::vector<const snlm_job*> js;
+    std::vector<char*> mids;
+    for (int i = 0; i < n; ++i) {
+        const char* why = check_job(&jobs[i]);
+        if (why) return fail(c, SNLM_EINVAL, std::string("job ") + std::to_string(i) + ": " + why);
+        if (jobs[i].kernel == SNLM_BOX && jobs[i].sum != SNLM_SUM_BLOCK)
+            return fail(c, SNLM_EINVAL, "batched launches use block-restarted sums");
+        js.push_back(&jobs[i]);
+        mids.push_back(c->arena + need);
+        need += mid_bytes(jobs[i].H, jobs[i].W);
+    }
+    if (need > c->arena_bytes) return fail(c, SNLM_ENOMEM, "batch intermediates exceed the arena");
+    HIP_CHECK(c, hipSetDevice(c->device));
+    std::vector<ClassPlan> plans;
+    plan_classes(c, js, mids, plans);
+    if (c->slots.size() < plans.size()) c->slots.resize(plans.size());
+    int rc = fence_in(c, c->work);
+    if (rc) return rc;
+    for (size_t k = 0; k < plans.size(); ++k) {
+        rc = upload_class(c, c->slots[k], plans[k], c->work);
+        if (!rc) rc = launch_class(c, c->slots[k], c->work, c->d_status, true);
+        if (rc) return rc;
+    }
+    c->last_batch_hash = hash;
+    c->last_batch_classes = (int)plans.size();
+    return fence_out(c, c->work);
+}
+
+int snlm_sync(snlm_ctx* c) {
+    if (!c) return SNLM_EINVAL;
+    HIP_CHECK(c, hipSetDevice(c->device));
+    HIP_CHECK(c, hipStreamSynchronize(c->work));
+    HIP_CHECK(c, hipStreamSynchronize(c->user));
+    uint32_t st = 0;
+    HIP_CHECK(c, hipMemcpy(&st, c->d_status, sizeof(st), hipMemcpyDeviceToHost));
+    if (st) {
+        HIP_CHECK(c, hipMemset(c->d_status, 0, sizeof(uint32_t)));
+        return fail(c, SNLM_EDEVICE, "a batched launch gave up waiting for a dependency");
+    }
+    return SNLM_OK;
+}
+
+int snlm_plan_seg_len(snlm_ctx* c, const snlm_job* j, int pass) {
+    if (!c || check_job(j) || pass < 0 || pass > 1) return SNLM_EINVAL;
+    PassDesc d;
+    fill_pass(d, *j, pass, nullptr, chosen_seg_len(c, *j, pass));
+    return d.seg_len;
+}
+
+int snlm_autotune(snlm_ctx* c, const snlm_job* probe, int* best) {
+    if (!c) return SNLM_EINVAL;
+    const char* why = check_job(probe);
+    if (why) return fail(c, SNLM_EINVAL, why);
+    if (probe->kernel == SNLM_BOX && probe->sum != SNLM_SUM_BLOCK)
+        return fail(c, SNLM_EINVAL, "only block-restarted sums are tiled");
+    if (mid_bytes(probe->H, probe->W) > c->arena_bytes) return fail(c, SNLM_ENOMEM, "arena too small");
+    HIP_CHECK(c, hipSetDevice(c->device));
+    hipEvent_t e0, e1;
+    HIP_CHECK(c, hipEventCreate(&e0));
+    HIP_CHECK(c, hipEventCreate(&e1));
+    int chosen[2] = {0, 0};
+    for (int pass = 0; pass < 2; ++pass) {
+        const bool rows = (pass == 0) == (probe->order == SNLM_ROW_COL);
+        const int n = rows ? probe->W : probe->H;
+        const int nlines = rows ? probe->H : probe->W;
+        const int nchunks = (n + kChunk - 1) / kChunk;
+        float best_ms = 1e30f;
+        const void* fn = kernel_fn(*probe, pass);
+        for (int cps = 1; cps <= nchunks; cps *= 2) {
+            PassDesc d;
+            fill_pass(d, *probe, pass, c->arena, cps * kChunk);
+            float ms_sum = 0.0f;
+            for (int rep = 0; rep < 4; ++rep) {
+                HIP_CHECK(c, hipEventRecord(e0, c->user));
+                for (int it = 0; it < 3; ++it) {
+                    int rc = launch_direct(c, fn, d, c->user, false);
+                    if (rc) return rc;
+                }
+                HIP_CHECK(c, hipEventRecord(e1, c->user));
+                HIP_CHECK(c, hipEventSynchronize(e1));
+                float ms = 0;
+                HIP_CHECK(c, hipEventElapsedTime(&ms, e0, e1));
+                if (rep > 0) ms_sum += ms;  // first repetition warms up
+            }
+            if (ms_sum < best_ms) {
+                best_ms = ms_sum;
+                chosen[pass] = cps * kChunk;
+            }
+            if (cps >= 64) break;
+        }
+        std::lock_guard<std::mutex> g(c->tune_mu);
+        c->tuned[TuneKey{probe->S, probe->K, variant_of(*probe), size_class(n), size_class(nlines)}] =
+            chosen[pass];
+        ++c->tune_epoch;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best) *best = chosen[0];
+    return SNLM_OK;
+}
+
+int snlm_autotune_save(snlm_ctx* c, const char* path) {
+    if (!c || !path) return SNLM_EINVAL;
+    FILE* f = std::fopen(path, "w");
+    if (!f) return fail(c, SNLM_EINVAL, "cannot open file");
+    std::lock_guard<std::mutex> g(c->tune_mu);
+    std::fprintf(f, "{\"arch\": \"gfx950\", \"entries\": [");
+    bool first = true;
+    for (auto& kv : c->tuned) {
+        std::fprintf(f, "%s\n  {\"S\": %d, \"K\": %d, \"variant\": %d, \"n_class\": %d, \"lines_class\": %d, \"seg_len\": %d}",
+                     first ? "" : ",", kv.first.S, kv.first.K, kv.first.var, kv.first.nclass,
+                     kv.first.lclass, kv.second);
+        first = false;
+    }
+    std::fprintf(f, "\n]}\n");
+    std::fclose(f);
+    return SNLM_OK;
+}
+
+int snlm_autotune_load(snlm_ctx* c, const char* path) {
+    if (!c || !path) return SNLM_EINVAL;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return fail(c, SNLM_EINVAL, "cannot open file");
+    std::string text;
+    char buf[4096];
+    size_t r;
+    while ((r = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, r);
+    std::fclose(f);
+    std::lock_guard<std::mutex> g(c->tune_mu);
+    size_t pos = 0;
+    int loaded = 0;
+    while ((pos = text.find("{\"S\":", pos)) != std::string::npos) {
+        TuneKey k;
+        int seg = 0;
+        if (std::sscanf(text.c_str() + pos,
+                        "{\"S\": %d, \"K\": %d, \"variant\": %d, \"n_class\": %d, \"lines_class\": %d, \"seg_len\": %d}",
+                        &k.S, &k.K, &k.var, &k.nclass, &k.lclass, &seg) == 6 &&
+            seg > 0 && seg % kChunk == 0) {
+            c->tuned[k] = seg;
+            ++c->tune_epoch;
+            ++loaded;
+        }
+        pos += 5;
+    }
+    return loaded > 0 ? SNLM_OK : fail(c, SNLM_EINVAL, "no entries");
+}
+
+int snlm_timing(snlm_ctx* c, int enable, double* batch_ms, int* batch_n, double* direct_ms,
+                int* direct_n) {
+    if (!c) return SNLM_EINVAL;
+    HIP_CHECK(c, hipSetDevice(c->device));
+    double sums[2] = {0.0, 0.0};
+    int counts[2] = {0, 0};
+    std::vector<std::pair<hipEvent_t, hipEvent_t>>* lists[2] = {&c->t_batch, &c->t_direct};
+    for (int k = 0; k < 2; ++k) {
+        for (auto& ev : *lists[k]) {
+            if (!enable) {
+                HIP_CHECK(c, hipEventSynchronize(ev.second));
+                float ms = 0.0f;
+                HIP_CHECK(c, hipEventElapsedTime(&ms, ev.first, ev.second));
+                sums[k] += ms;
+                counts[k] += 1;
+            }
+            c->t_pool.push_back(ev);
+        }
+        lists[k]->clear();
+    }
+    c->timing = enable != 0;
+    if (batch_ms) *batch_ms = sums[0];
+    if (batch_n) *batch_n = counts[0];
+    if (direct_ms) *direct_ms = sums[1];
+    if (direct_n) *direct_n = counts[1];
+    return SNLM_OK;
+}
+
+int snlm_submit(snlm_ctx* c, const snlm_job* j, uint64_t* ticket) {
+    if (!c || !ticket) return SNLM_EINVAL;
+    const char* why = check_job(j);
+    if (why) return fail(c, SNLM_EINVAL, why);
+    if (j->kernel == SNLM_BOX && j->sum != SNLM_SUM_BLOCK)
+        return fail(c, SNLM_EINVAL, "served jobs use block-restarted sums");
+    const size_t need = snlm_serving_bytes(j->H, j->W, j->dtype);
+    if (need > c->arena_bytes) return fail(c, SNLM_ENOMEM, "job can never fit the arena");
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (c->closing) return SNLM_ECLOSED;
+    if (!c->sched_started) {
+        int rc = start_scheduler(c);
+        if (rc) return rc;
+    }
+    auto sj = std::make_shared<ServeJob>();
+    sj->ticket = c->next_ticket++;
+    sj->job = *j;
+    sj->need = need;
+    sj->t_submit = now_us();
+    c->pending.push_back(sj);
+    c->jobs[sj->ticket] = sj;
+    *ticket = sj->ticket;
+    c->cv.notify_all();
+    return SNLM_OK;
+}
+
+int snlm_poll(snlm_ctx* c, uint64_t ticket) {
+    if (!c) return SNLM_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->jobs.find(ticket);
+    if (it == c->jobs.end()) return SNLM_ENOTICKET;
+    const int st = it->second->status;
+    if (st == SNLM_PENDING) return SNLM_PENDING;
+    c->jobs.erase(it);
+    return st;
+}
+
+int snlm_job_times(snlm_ctx* c, uint64_t ticket, double* ts, double* ta, double* td) {
+    if (!c) return SNLM_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->jobs.find(ticket);
+    if (it == c->jobs.end()) return SNLM_ENOTICKET;
+    if (ts) *ts = it->second->t_submit;
+    if (ta) *ta = it->second->t_admit;
+    if (td) *td = it->second->t_done;
+    return SNLM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,559 @@
+// Device side of the separable PatchLift non-local means library (gfx950).
+//
+// One pass of separable NLM (Sec. 3) filters a set of independent lines (the
+// rows or the columns of an image) with the 1D NLM of eq. 1dNLM.  Here one
+// lane owns one line and walks a segment of it serially, in chunks of kChunk
+// samples; a wave therefore filters 64 adjacent lines at once, with no
+// cross-lane traffic at all.  For the column pass the 64 lanes read 64
+// adjacent columns (coalesced); for the row pass each lane reads its own row.
+//
+// Per lane, per offset s = 1..S and centre u of the chunk, the pair (u, u+s) is
+// visited once (the band symmetry of Sec. 2.1: w(u,u+s) = w(u+s,u)):
+//   lift     D_s(v) = (a x(v) - a x(v+s))^2, a = sqrt(log2 e)/h (difference form
+//            of eqs. tensor/convn/lift; no cancellation of the tensor form)
+//   window   box:   R_s(u) = sum_{k=-K..K} D_s(u+k), carried as the recursion of
+//                   eq. recursion: R_s(u) = R_s(u-1) + D_s(u+K) - D_s(u-K-1),
+//                   re-initialised directly at line-relative positions
+//                   u = -S (mod kChunk) ("block restart"), or never ("plain"),
+//                   or carried with Kahan compensation ("kahan");
+//            gauss: R_s(u) = sum_k g(k) D_s(u+k), an exact (2K+1)-tap FIR.
+//   weight   w = exp2(-R_s(u)) = exp(-d2/h^2)            (eq. 1dNLM)
+//   average  P(u) += w x(u+s), Q(u) += w, P(u+s) += w x(u), Q(u+s) += w
+//            (P, Q start at x(u), 1: the s = 0 term), y(u) = P(u)/Q(u).
+//
+// Lines are extended by half-sample symmetric reflection.  A segment
+// [a, b) of a line (a a multiple of kChunk) needs the pairs (u, u+s) with
+// u in [a-S, a) for its first centres; those are computed in a "pre-chunk"
+// that repeats, operation for operation, what the previous chunk would have
+// done for them.  Every output therefore has bit-identical arithmetic however
+// a line is split into segments (plain launch, batched launch, any tuned
+// segment length).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace snlm {
+
+constexpr int kChunk = 16;  // samples per chunk; also the block-restart period
+constexpr int kMaxS = 16;   // search half-width limit (S <= kChunk)
+constexpr int kMaxK = 8;    // patch half-width limit
+constexpr int kLanes = 64;  // lines per wave
+constexpr uint32_t kRsrcWord3 = 0x00020000u;  // raw buffer, 32-bit data, gfx9 family
+
+// One pass over the lines of one image.
+struct PassDesc {
+    const void* in;        // line data (FP32, or FP16 when in_f16)
+    float* out;            // FP32 output
+    uint32_t in_bytes;     // extent of the input buffer (bounds for buffer ops)
+    uint32_t out_bytes;    // extent of the output buffer
+    int32_t nlines;        // number of lines
+    int32_t n;             // samples per line
+    int32_t in_line;       // element stride between lines (input)
+    int32_t in_pos;        // element stride between samples of a line (input)
+    int32_t out_line;      // element stride between lines (output)
+    int32_t out_pos;       // element stride between samples (output)
+    int32_t in_f16;        // input stored as FP16
+    int32_t restart;       // 1: block-restarted running sums (box only)
+    int32_t seg_len;       // samples per segment (multiple of kChunk)
+    int32_t nseg;          // segments per line = ceil(n / seg_len)
+    int32_t ngroups;       // groups of 64 lines = ceil(nlines / 64)
+    float alpha;           // lift scale a = sqrt(log2 e) / h  (2^-64 when h = inf)
+    float inv_alpha;       // 1 / a
+    float taps[kMaxK + 1]; // Gaussian taps g(0..K) (g(0) = 1)
+};
+
+// A batch: jobs, each with two passes, and a flat list of tiles.  Tiles of
+// every first pass come before tiles of any second pass.
+struct BatchJob {
+    PassDesc pass[2];
+    int32_t tiles[2];      // tiles per pass (ngroups * nseg)
+    int32_t tile_base[2];  // index of the pass's first tile in the flat list
+};
+
+struct BatchHeader {
+    int32_t njobs;
+    int32_t ntiles_first;  // tiles of all first passes
+    int32_t ntiles;        // all tiles
+    uint32_t spin_limit;   // bound on dependency polls before giving up
+};
+
+// Kernel arguments.  direct mode (table == nullptr): grid = ngroups * nseg
+// workgroups of one wave; tile = blockIdx.x.  Batch mode: persistent grid
+// claiming tiles from the table.
+struct KernelArgs {
+    PassDesc direct;
+    const BatchHeader* hdr;
+    const BatchJob* jobs;
+    const uint32_t* tile_job;  // tile -> job index
+    uint32_t* counters;        // [1 + j] finished first-pass tiles of job j
+    uint32_t* claim;           // claim counter of this launch
+    uint32_t* status;          // set non-zero when a dependency wait gives up
+    int32_t tile_lo, tile_hi;  // tiles [lo, hi) of the flat list handled by this launch
+    int32_t wait;              // second-pass tiles wait for their job's first pass
+};
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
+                                             (int)kRsrcWord3);
+}
+
+// Half-sample symmetric reflection into [0, n) (period 2n).  The position is
+// the same for every lane of a wave, so this runs on the scalar unit.
+__device__ __forceinline__ int refl(int p, int n) {
+    while ((unsigned)p >= (unsigned)n) p = p < 0 ? -1 - p : 2 * n - 1 - p;
+    return p;
+}
+
+constexpr int kStage = kChunk + 1;   // LDS row stride of the output tile (odd: no bank conflicts)
+constexpr int kRowF32 = 20;          // input tile: floats per line (16 + up to 3 of alignment)
+constexpr int kRowF16 = 24;          // input tile: halves per line (16 + up to 7 of alignment)
+constexpr int kVecF32 = 5;           // 16-byte loads per lane for an FP32 input tile
+constexpr int kVecF16 = 3;           // 16-byte loads per lane for an FP16 input tile
+constexpr int kTileIn = kLanes * kRowF32;   // floats of LDS for the input tile
+constexpr int kTileOut = kLanes * kStage;   // floats of LDS for the output tile
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// Reinterprets a 32-bit word as a float.  Vector elements must pass through a
+// scalar first: __builtin_bit_cast applied to an element expression of an
+// ext_vector_type reads element 0 whatever the index.
+__device__ __forceinline__ float as_float(unsigned u) { return __builtin_bit_cast(float, u); }
+
+// Loads and stores of one lane's line.  Chunks of kChunk samples of lines that
+// are contiguous in memory (the row pass) go through an LDS transpose tile:
+// the wave fetches its 64 lines with 4-element vector loads from 4-element
+// aligned addresses (each line's first sample may sit anywhere inside its
+// first vector), and writes results back the same way, instead of every lane
+// touching its own cache line with each 4-byte access.
+struct LineIO {
+    __amdgpu_buffer_rsrc_t rin, rout;
+    int32_t in_base_b;   // byte offset of this lane's line (input)
+    int32_t out_base_b;  // byte offset of this lane's line (output)
+    int32_t in_pos_b;    // byte stride between samples (input)
+    int32_t out_pos_b;   // byte stride between samples (output)
+    int32_t in_line;     // element stride between lines (input)
+    int32_t out_line;    // element stride between lines (output)
+    int32_t line0;       // first line of this wave
+    int32_t nlines;
+    int32_t lane;
+    int32_t n;
+    bool f16;
+    bool stage_in;       // lines contiguous in the input: use the LDS tile
+    bool stage_out;      // lines contiguous and 16-byte aligned in the output
+    float* tile_in;      // input tile (kTileIn floats of LDS)
+    float* tile_out;     // output tile (kTileOut floats of LDS)
+
+    // count samples starting at position p (reflected), into v[0..count)
+    template <int COUNT>
+    __device__ __forceinline__ void load(int p, float* v) const {
+        if (f16) {
+#pragma unroll
+            for (int t = 0; t < COUNT; ++t) {
+                int off = in_base_b + refl(p + t, n) * in_pos_b;
+                unsigned short bits = __builtin_amdgcn_raw_buffer_load_b16(rin, off, 0, 0);
+                v[t] = (float)__builtin_bit_cast(_Float16, bits);
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < COUNT; ++t) {
+                int off = in_base_b + refl(p + t, n) * in_pos_b;
+                v[t] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rin, off, 0, 0));
+            }
+        }
+    }
+
+    // Whether the chunk of samples [p, p + kChunk) goes through the LDS tile.
+    __device__ __forceinline__ bool chunk_staged(int p) const {
+        return stage_in && p >= 0 && p + kChunk <= n;
+    }
+
+    // First half of a chunk load: start the global loads.  Unstaged: into v.
+    // Staged: 16-byte loads that write LDS directly (no registers in flight).
+    // The tile holds 64 lines of kRowF32 floats (or kRowF16 halves) starting
+    // at each line's aligned element (line * in_line + p) & ~3 (& ~7 for FP16);
+    // load j = lane + 64 r covers line j / V, vector j % V of that line, and
+    // lands at LDS byte 16 j.  Reads past a line's end stay inside the buffer
+    // or return 0 (buffer bounds) and are never used.
+    __device__ __forceinline__ void issue_chunk(int p, float* v) const {
+        if (!chunk_staged(p)) {
+            load<kChunk>(p, v);
+            return;
+        }
+        typedef __attribute__((address_space(3))) void* lds_ptr;
+        if (f16) {
+#pragma unroll
+            for (int r = 0; r < kVecF16; ++r) {
+                const int j = lane + 64 * r;
+                const int line = min(line0 + j / 3, nlines - 1);
+                const int e = ((line * in_line + p) & ~7) + 8 * (j % 3);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, (lds_ptr)(tile_in + 256 * r), 16, e * 2, 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < kVecF32; ++r) {
+                const int j = lane + 64 * r;
+                const int line = min(line0 + j / 5, nlines - 1);
+                const int e = ((line * in_line + p) & ~3) + 4 * (j % 5);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, (lds_ptr)(tile_in + 256 * r), 16, e * 4, 0, 0, 0);
+            }
+        }
+    }
+
+    // Second half: for a staged chunk, wait for the loads and read this lane's
+    // own samples p .. p + kChunk - 1 out of the tile.
+    __device__ __forceinline__ void finish_chunk(int p, float* v) const {
+        if (!chunk_staged(p)) return;
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the LDS-bound loads have landed
+        __syncthreads();
+        const int line = min(line0 + lane, nlines - 1);
+        if (f16) {
+            const int m = (line * in_line + p) & 7;
+            const _Float16* th = reinterpret_cast<const _Float16*>(tile_in);
+#pragma unroll
+            for (int t = 0; t < kChunk; ++t) v[t] = (float)th[lane * kRowF16 + m + t];
+        } else {
+            const int m = (line * in_line + p) & 3;
+#pragma unroll
+            for (int t = 0; t < kChunk; ++t) v[t] = tile_in[lane * kRowF32 + m + t];
+        }
+        __syncthreads();
+    }
+
+    __device__ __forceinline__ void store(int p, float v) const {
+        int off = out_base_b + p * out_pos_b;
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rout, off, 0, 0);
+    }
+
+    // Stores this lane's outputs y[0..kChunk) at positions c0.. (only those
+    // below end, and only for active lanes).
+    // stage_out requires every line start and c0 to be 4-element aligned, so
+    // the 16-byte stores below are aligned.
+    __device__ __forceinline__ void store_chunk(int c0, int end, bool active, const float* y) const {
+        if (stage_out && c0 + kChunk <= end) {
+#pragma unroll
+            for (int i = 0; i < kChunk; ++i) tile_out[lane * kStage + i] = y[i];
+            __syncthreads();
+            const int col = (lane & 3) * 4;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = (lane >> 2) + 16 * r;
+                u32x4 w;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) w[e] = __builtin_bit_cast(unsigned, tile_out[row * kStage + col + e]);
+                if (line0 + row < nlines) {
+                    const int off = ((line0 + row) * out_line + c0 + col) * 4;
+                    __builtin_amdgcn_raw_buffer_store_b128(w, rout, off, 0, 0);
+                }
+            }
+            __syncthreads();
+            return;
+        }
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < kChunk; ++i)
+                if (c0 + i < end) store(c0 + i, y[i]);
+        }
+    }
+};
+
+// Filters samples [seg_a, seg_b) of one line.  seg_a is a multiple of kChunk.
+template <int S, int K, bool GAUSS, bool KAHAN>
+__device__ __forceinline__ void run_segment(const PassDesc& d, const LineIO& io, bool active,
+                                            int seg_a, int seg_b) {
+    constexpr int C = kChunk;
+    constexpr int NX = C + S + 2 * K + 1;  // x window: positions c0-K-1 .. c0+C+S+K-1
+    constexpr int NP = C + S;              // accumulators: centres c0 .. c0+C+S-1
+    constexpr int ND = C + 2 * K;          // lifted samples of one diagonal (Gaussian)
+    constexpr int R0 = (C - S) % C;        // restart offset within a chunk
+    constexpr int XO = K + 1;              // x index of centre c0
+    static_assert(S >= 1 && S <= kMaxS && K >= 0 && K <= kMaxK, "parameter range");
+
+    // Everything runs on the scaled samples xs = a x: the lift then needs no
+    // multiply, and the average of scaled samples is unscaled once per output
+    // (y = (P / Q) / a).
+    const float alpha = d.alpha;
+    const float inv_alpha = d.inv_alpha;
+    const bool restart = d.restart != 0;
+    float xs[NX], P[NP], Q[NP], nx[C];  // nx: the next chunk's samples
+    float R[S];
+    float Rc[KAHAN ? S : 1];
+    float Dv[GAUSS ? ND : 1];
+    float g[K + 1];
+#pragma unroll
+    for (int k = 0; k <= K; ++k) g[k] = d.taps[k];
+
+    // ---- window for the pre-chunk at c0 = seg_a - C ----
+    int c0 = seg_a - C;
+    io.template load<NX>(c0 - K - 1, xs);
+#pragma unroll
+    for (int j = 0; j < NX; ++j) xs[j] = alpha * xs[j];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        P[i] = xs[i + XO];
+        Q[i] = 1.0f;
+    }
+    io.issue_chunk(seg_a + S + K, nx);
+
+    // Lifted diagonal D_s(v) for v = c0-K+m, m in [m0, ND) (Gaussian).
+    auto lift_diag = [&](int s, int m0) {
+#pragma unroll
+        for (int m = 0; m < ND; ++m) {
+            if (m < m0) continue;
+            float dd = xs[m + 1] - xs[m + 1 + s];
+            Dv[m] = dd * dd;
+        }
+    };
+    // Gaussian FIR of the lifted diagonal at centre index i.
+    auto gauss_d2 = [&](int i) -> float {
+        float r = Dv[i + K];
+#pragma unroll
+        for (int k = 1; k <= K; ++k) r = __builtin_fmaf(g[k], Dv[i + K - k] + Dv[i + K + k], r);
+        return r;
+    };
+    // Direct window sum of the lifted diagonal at centre index i (box).
+    auto box_init = [&](int i, int s) -> float {
+        float r = 0.0f;
+#pragma unroll
+        for (int k = -K; k <= K; ++k) {
+            float dd = xs[i + XO + k] - xs[i + XO + k + s];
+            r = (k == -K) ? dd * dd : __builtin_fmaf(dd, dd, r);
+        }
+        return r;
+    };
+    // One step of the recursion of eq. recursion at centre index i.
+    auto box_slide = [&](int i, int s, int si) {
+        float de = xs[i + 2 * K + 1] - xs[i + 2 * K + 1 + s];  // enters: D_s(u+K)
+        float dl = xs[i] - xs[i + s];                          // leaves: D_s(u-K-1)
+        if constexpr (KAHAN) {
+            float t = __builtin_fmaf(de, de, -(dl * dl));
+            float y = t - Rc[si];
+            float sum = R[si] + y;
+            Rc[si] = (sum - R[si]) - y;
+            R[si] = sum;
+        } else {
+            R[si] = __builtin_fmaf(-dl, dl, __builtin_fmaf(de, de, R[si]));
+        }
+    };
+
+    // ---- pre-chunk: pairs (u, u+s) with u in [seg_a - s, seg_a) ----
+#pragma unroll
+    for (int s = 1; s <= S; ++s) {
+        const int si = s - 1;
+        if constexpr (GAUSS) lift_diag(s, C - s);
+#pragma unroll
+        for (int i = R0; i < C; ++i) {
+            float r;
+            if constexpr (GAUSS) {
+                if (i < C - s) continue;
+                r = gauss_d2(i);
+            } else {
+                if (i == R0) {
+                    R[si] = box_init(i, s);
+                    if constexpr (KAHAN) Rc[si] = 0.0f;
+                } else {
+                    box_slide(i, s, si);
+                }
+                if (i < C - s) continue;
+                r = R[si];
+            }
+            float w = __builtin_amdgcn_exp2f(-__builtin_fabsf(r));
+            P[i + s] = __builtin_fmaf(w, xs[i + XO], P[i + s]);
+            Q[i + s] += w;
+        }
+    }
+
+    // ---- main chunks ----
+    for (c0 = seg_a;; c0 += C) {
+        io.finish_chunk(c0 + S + K, nx);
+        // shift the window by one chunk
+#pragma unroll
+        for (int j = 0; j < NX - C; ++j) xs[j] = xs[j + C];
+#pragma unroll
+        for (int t = 0; t < C; ++t) xs[NX - C + t] = alpha * nx[t];
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            P[i] = P[i + C];
+            Q[i] = Q[i + C];
+        }
+#pragma unroll
+        for (int i = S; i < NP; ++i) {
+            P[i] = xs[i + XO];
+            Q[i] = 1.0f;
+        }
+        const bool has_next = c0 + C < seg_b;
+        if (has_next) io.issue_chunk(c0 + C + S + K, nx);
+
+#pragma unroll
+        for (int s = 1; s <= S; ++s) {
+            const int si = s - 1;
+            // Keep the scheduler from interleaving offsets: one diagonal at a
+            // time bounds the live registers (and so raises occupancy).
+            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (GAUSS) lift_diag(s, 0);
+#pragma unroll
+            for (int i = 0; i < C; ++i) {
+                float r;
+                if constexpr (GAUSS) {
+                    r = gauss_d2(i);
+                } else {
+                    box_slide(i, s, si);
+                    if (i == R0) {
+                        // block restart: a select on a wave-uniform flag keeps
+                        // the chunk one straight-line block
+                        const float fresh = box_init(i, s);
+                        R[si] = restart ? fresh : R[si];
+                        if constexpr (KAHAN) Rc[si] = restart ? 0.0f : Rc[si];
+                    }
+                    r = R[si];
+                }
+                float w = __builtin_amdgcn_exp2f(-__builtin_fabsf(r));
+                P[i] = __builtin_fmaf(w, xs[i + XO + s], P[i]);
+                Q[i] += w;
+                P[i + s] = __builtin_fmaf(w, xs[i + XO], P[i + s]);
+                Q[i + s] += w;
+            }
+        }
+
+        float y[C];
+#pragma unroll
+        for (int i = 0; i < C; ++i) y[i] = (P[i] * __builtin_amdgcn_rcpf(Q[i])) * inv_alpha;
+        // Materialise all outputs before the (partly masked) stores, so that
+        // the compiler does not sink the last accumulations into the store
+        // branches and split the chunk into small blocks.
+#pragma unroll
+        for (int i = 0; i < C; i += 4)
+            asm volatile("" ::"v"(y[i]), "v"(y[i + 1]), "v"(y[i + 2]), "v"(y[i + 3]));
+        io.store_chunk(c0, seg_b, active, y);
+        if (!has_next) break;
+    }
+}
+
+// Copy / convert pass for S = 0 (the 1D NLM is then the identity).
+__device__ __forceinline__ void run_copy(const LineIO& io, bool active, int seg_a, int seg_b) {
+    for (int p = seg_a; p < seg_b; ++p) {
+        float v[1];
+        io.template load<1>(p, v);
+        if (active) io.store(p, v[0]);
+    }
+}
+
+// ROWS: the kernel variant for passes whose lines are contiguous in memory
+// (it carries the LDS transpose tiles); column-pass variants compile the
+// tiles out and so keep fewer registers live.
+template <bool ROWS>
+__device__ __forceinline__ LineIO make_io(const PassDesc& d, int line0, int lane, float* tiles) {
+    LineIO io;
+    const int line = min(line0 + lane, d.nlines - 1);
+    io.rin = make_rsrc(d.in, d.in_bytes);
+    io.rout = make_rsrc(d.out, d.out_bytes);
+    const int esz = d.in_f16 ? 2 : 4;
+    io.in_base_b = line * d.in_line * esz;
+    io.in_pos_b = d.in_pos * esz;
+    io.in_line = d.in_line;
+    io.out_base_b = line * d.out_line * 4;
+    io.out_pos_b = d.out_pos * 4;
+    io.out_line = d.out_line;
+    io.line0 = line0;
+    io.nlines = d.nlines;
+    io.lane = lane;
+    io.n = d.n;
+    io.f16 = d.in_f16 != 0;
+    io.stage_in = ROWS && d.in_pos == 1 && ((uintptr_t)d.in & 15) == 0;
+    io.stage_out = ROWS && d.out_pos == 1 && (d.out_line & 3) == 0 && ((uintptr_t)d.out & 15) == 0;
+    io.tile_in = tiles;
+    io.tile_out = tiles + kTileIn;
+    return io;
+}
+
+template <int S, int K, bool GAUSS, bool KAHAN, bool ROWS>
+__device__ __forceinline__ void run_tile(const PassDesc& d, int tile, float* tiles) {
+    const int group = tile % d.ngroups;
+    const int seg = tile / d.ngroups;
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int line0 = group * kLanes;
+    const bool active = line0 + lane < d.nlines;
+    const int a = seg * d.seg_len;
+    const int b = min(a + d.seg_len, d.n);
+    const LineIO io = make_io<ROWS>(d, line0, lane, tiles);
+    if constexpr (S == 0) {
+        run_copy(io, active, a, b);
+    } else {
+        run_segment<S, K, GAUSS, KAHAN>(d, io, active, a, b);
+    }
+}
+
+// Loads a table entry the whole wave agrees on and keeps it in scalar
+// registers (the compiler cannot prove on its own that a value loaded through
+// a wave-uniform index is uniform).
+template <typename T>
+__device__ __forceinline__ T load_uniform(const T* src) {
+    static_assert(sizeof(T) % 4 == 0, "word-sized");
+    T v;
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(src);
+    uint32_t* o = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) o[i] = __builtin_amdgcn_readfirstlane(w[i]);
+    return v;
+}
+
+// One kernel per (S, K, kernel, compensation, row/column variant).
+// Workgroup = one wave.
+template <int S, int K, bool GAUSS, bool KAHAN, bool ROWS>
+__global__ __launch_bounds__(kLanes) void snlm_kernel(KernelArgs args) {
+    const bool batch = args.hdr != nullptr;
+    BatchHeader hdr = {0, 0, 0, 0u};
+    if (batch) hdr = load_uniform(args.hdr);
+    __shared__ uint32_t claimed;
+    __shared__ __attribute__((aligned(16))) float tiles[ROWS ? kTileIn + kTileOut : 1];
+    for (int iter = 0;; ++iter) {
+        PassDesc d;
+        int tile, job = 0, pass = 0;
+        if (!batch) {
+            if (iter > 0) break;
+            d = args.direct;
+            tile = blockIdx.x;
+        } else {
+            if (threadIdx.x == 0) claimed = atomicAdd(args.claim, 1u);
+            __syncthreads();
+            const uint32_t t = __builtin_amdgcn_readfirstlane(claimed) + (uint32_t)args.tile_lo;
+            __syncthreads();
+            if (t >= (uint32_t)args.tile_hi) break;
+            pass = t < (uint32_t)hdr.ntiles_first ? 0 : 1;
+            job = (int)__builtin_amdgcn_readfirstlane(args.tile_job[t]);
+            tile = (int)t - (int)__builtin_amdgcn_readfirstlane(args.jobs[job].tile_base[pass]);
+            if (pass == 1 && args.wait) {
+                // Wait until every first-pass tile of this job has been written:
+                // poll with relaxed device-scope loads (no cache invalidation per
+                // poll), then one acquire fence before reading the intermediate.
+                const uint32_t need = __builtin_amdgcn_readfirstlane(args.jobs[job].tiles[0]);
+                uint32_t polls = 0;
+                bool ok = true;
+                while (__hip_atomic_load(&args.counters[1 + job], __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT) < need) {
+                    if (++polls > hdr.spin_limit) {
+                        ok = false;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(4);
+                }
+                if (!ok) {
+                    if (threadIdx.x == 0) atomicOr(args.status, 1u);
+                    break;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+            d = load_uniform(&args.jobs[job].pass[pass]);
+        }
+        run_tile<S, K, GAUSS, KAHAN, ROWS>(d, tile, tiles);
+        if (batch && pass == 0 && args.wait) {
+            // publish this tile's intermediate rows (one release per tile)
+            __syncthreads();
+            if (threadIdx.x == 0)
+                __hip_atomic_fetch_add(&args.counters[1 + job], 1u, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+}  // namespace snlm

@@ -1,0 +1,36 @@
+// Instantiates every kernel variant for one search half-width S, given on the
+// compiler command line as -DSNLM_S=<S>, and registers their entry points.
+#include "snlm_registry.hpp"
+
+#ifndef SNLM_S
+#error "compile with -DSNLM_S=<0..16>"
+#endif
+
+namespace snlm {
+namespace {
+
+template <int K>
+void register_k(KernelRegistry* reg) {
+    if constexpr (SNLM_S == 0) {
+        const void* f = (const void*)&snlm_kernel<0, 0, false, false, false>;
+        for (int v = 0; v < kNumVariants; ++v)
+            for (int r = 0; r < 2; ++r) reg->fn[0][K][v][r] = f;
+    } else {
+        reg->fn[SNLM_S][K][kVarBox][0] = (const void*)&snlm_kernel<SNLM_S, K, false, false, false>;
+        reg->fn[SNLM_S][K][kVarBox][1] = (const void*)&snlm_kernel<SNLM_S, K, false, false, true>;
+        reg->fn[SNLM_S][K][kVarBoxKahan][0] = (const void*)&snlm_kernel<SNLM_S, K, false, true, false>;
+        reg->fn[SNLM_S][K][kVarBoxKahan][1] = (const void*)&snlm_kernel<SNLM_S, K, false, true, true>;
+        reg->fn[SNLM_S][K][kVarGauss][0] = (const void*)&snlm_kernel<SNLM_S, K, true, false, false>;
+        reg->fn[SNLM_S][K][kVarGauss][1] = (const void*)&snlm_kernel<SNLM_S, K, true, false, true>;
+    }
+    if constexpr (K < kMaxK) register_k<K + 1>(reg);
+}
+
+}  // namespace
+}  // namespace snlm
+
+#define SNLM_CAT2(a, b) a##b
+#define SNLM_CAT(a, b) SNLM_CAT2(a, b)
+extern "C" void SNLM_CAT(snlm_register_s, SNLM_S)(snlm::KernelRegistry* reg) {
+    snlm::register_k<0>(reg);
+}

@@ -1,0 +1,39 @@
+// Table of compiled kernel entry points, filled by one registration function per
+// search half-width S (each compiled in its own translation unit).
+#pragma once
+
+#include "snlm_device.hpp"
+
+namespace snlm {
+
+enum Variant { kVarBox = 0, kVarBoxKahan = 1, kVarGauss = 2, kNumVariants = 3 };
+
+// fn[S][K][variant][rows]: rows = 1 is the variant for passes whose lines are
+// contiguous in memory (LDS transpose tiles), rows = 0 for column passes.
+struct KernelRegistry {
+    const void* fn[kMaxS + 1][kMaxK + 1][kNumVariants][2];
+};
+
+}  // namespace snlm
+
+extern "C" {
+#define SNLM_DECLARE_REG(n) void snlm_register_s##n(snlm::KernelRegistry* reg);
+SNLM_DECLARE_REG(0)
+SNLM_DECLARE_REG(1)
+SNLM_DECLARE_REG(2)
+SNLM_DECLARE_REG(3)
+SNLM_DECLARE_REG(4)
+SNLM_DECLARE_REG(5)
+SNLM_DECLARE_REG(6)
+SNLM_DECLARE_REG(7)
+SNLM_DECLARE_REG(8)
+SNLM_DECLARE_REG(9)
+SNLM_DECLARE_REG(10)
+SNLM_DECLARE_REG(11)
+SNLM_DECLARE_REG(12)
+SNLM_DECLARE_REG(13)
+SNLM_DECLARE_REG(14)
+SNLM_DECLARE_REG(15)
+SNLM_DECLARE_REG(16)
+#undef SNLM_DECLARE_REG
+}

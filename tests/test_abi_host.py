@@ -1,0 +1,110 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+include/snlm.h declares, and rejects bad jobs before touching a device."""
+import math
+import os
+import re
+
+import pytest
+
+import paper_1407_2343_amd as snlm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "snlm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(snlm_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("snlm_create", "snlm_destroy", "snlm_denoise", "snlm_denoise_ex",
+                     "snlm_denoise_batch", "snlm_submit", "snlm_poll", "snlm_sync",
+                     "snlm_workspace_bytes", "snlm_strerror", "snlm_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = snlm.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_strerror_and_version():
+    assert snlm.strerror(0) == "ok"
+    assert "arena" in snlm.strerror(-2)
+    assert snlm.strerror(12345) == "unknown status"
+    assert "gfx950" in snlm.version()
+
+
+def test_workspace_bytes():
+    assert snlm.workspace_bytes(512, 512) == 512 * 512 * 4
+    assert snlm.workspace_bytes(3, 5) == 256  # rounded to 256 bytes
+    assert snlm.workspace_bytes(0, 5) == 0
+
+
+GOOD = dict(img=0x100000, out=0x900000, H=64, W=80, S=10, K=3, h=200.0)
+
+
+def job(**kw):
+    d = dict(GOOD)
+    d.update(kw)
+    return snlm.make_job(**d)
+
+
+def test_valid_job_passes():
+    assert snlm.validate(job())[0] == snlm.OK
+    assert snlm.validate(job(h=math.inf))[0] == snlm.OK
+    assert snlm.validate(job(S=0, K=0))[0] == snlm.OK
+    assert snlm.validate(job(S=16, K=8, kernel="gauss"))[0] == snlm.OK
+    assert snlm.validate(job(dtype="f16", sum="kahan"))[0] == snlm.OK
+
+
+@pytest.mark.parametrize("bad,reason", [
+    (dict(img=0), "non-NULL"),
+    (dict(out=0), "non-NULL"),
+    (dict(H=0), ">= 1"),
+    (dict(W=-3), ">= 1"),
+    (dict(ld_in=10), "pitches"),
+    (dict(ld_out=79), "pitches"),
+    (dict(S=17), "S out of range"),
+    (dict(S=-1), "S out of range"),
+    (dict(K=9), "K out of range"),
+    (dict(h=0.0), "h must be"),
+    (dict(h=-1.0), "h must be"),
+    (dict(h=float("nan")), "h must be"),
+    (dict(seg_len=20), "multiple of 16"),
+    (dict(out=0x100000 + 100), "overlaps"),
+    (dict(H=40000, W=40000), "2 GiB"),
+])
+def test_invalid_jobs_rejected(bad, reason):
+    rc, why = snlm.validate(job(**bad))
+    assert rc == snlm.EINVAL
+    assert reason in why
+
+
+def test_unknown_enums_rejected():
+    j = job()
+    j.kernel = 7
+    assert snlm.validate(j)[0] == snlm.EINVAL
+    j = job()
+    j.order = 2
+    assert snlm.validate(j)[0] == snlm.EINVAL
+    j = job()
+    j.sum = 9
+    assert snlm.validate(j)[0] == snlm.EINVAL
+    j = job()
+    j.dtype = 3
+    assert snlm.validate(j)[0] == snlm.EINVAL
+
+
+def test_null_context_calls_are_rejected():
+    lib = snlm.lib()
+    j = job()
+    import ctypes
+    assert lib.snlm_denoise_ex(None, ctypes.byref(j)) == snlm.EINVAL
+    assert lib.snlm_sync(None) == snlm.EINVAL
+    assert lib.snlm_poll(None, 1) == snlm.EINVAL
+    assert lib.snlm_destroy(None) == snlm.OK
+    assert lib.snlm_create(None, 0, None, None, 0) == snlm.EINVAL

@@ -1,0 +1,214 @@
+"""Batched launches, serving and precision variants on the GPU.
+
+* batch == plain: each image of a ragged batch, run in the persistent batched
+  launches (split and fused modes), is bitwise equal to its plain launch, and
+  within 1e-3 of the FP64 oracle.
+* serving: every served job is bitwise equal to the same job run alone, the
+  scheduler overlaps launches (a job admitted while an earlier one is still in
+  flight), and misuse is reported (ENOMEM, ENOTICKET).
+* precision: FP16/FP32 storage x block/plain/Kahan running sums on a large
+  image, checked against the oracle at sampled pixels.
+"""
+import math
+import os
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import TOL, max_abs, say
+from paper_1407_2343_amd.synth import noisy_image
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(arena, mode=None):
+    import paper_1407_2343_amd as snlm
+    old = os.environ.get("SNLM_BATCH_MODE")
+    if mode is not None:
+        os.environ["SNLM_BATCH_MODE"] = mode
+    try:
+        return snlm.Context(arena_bytes=arena)
+    finally:
+        if mode is not None:
+            if old is None:
+                os.environ.pop("SNLM_BATCH_MODE", None)
+            else:
+                os.environ["SNLM_BATCH_MODE"] = old
+
+
+def _ragged(n, seed, lo=40, hi=300):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        H = int(rng.integers(lo, hi))
+        W = int(rng.integers(lo, hi))
+        sig = float(rng.choice([10.0, 20.0, 30.0, 40.0]))
+        out.append((noisy_image(H, W, sig, seed * 100 + i), sig))
+    return out
+
+
+@pytest.mark.parametrize("mode", ["split", "fused"])
+def test_batch_equals_plain(mode):
+    import torch
+    import paper_1407_2343_amd as snlm
+    items = _ragged(12, 5)
+    ctx = _ctx(64 << 20, mode)
+    xs = [torch.from_numpy(im).to("cuda:0") for im, _ in items]
+    outs = ctx.denoise_batch(xs, 10, 3, [10 * s for _, s in items], "box", "row_col", sync=True)
+    # same batch again: replays the cached graph and tables
+    outs2 = ctx.denoise_batch(xs, 10, 3, [10 * s for _, s in items], "box", "row_col", sync=True)
+    for i, ((im, sig), x, o, o2) in enumerate(zip(items, xs, outs, outs2)):
+        say("batch", mode, i, im.shape)
+        alone = ctx.denoise(x, 10, 3, 10 * sig, "box", "row_col", sync=True)
+        assert torch.equal(o, alone), i
+        assert torch.equal(o2, alone), i
+        if i < 4:
+            ref = oracle.snlm(im.astype(np.float64), 10, 3, 10 * sig, "box", "row_col")
+            assert max_abs(o.cpu().numpy(), ref) <= TOL
+    ctx.close()
+
+
+def test_batch_mixed_classes():
+    """Several (S, K, kernel, order) classes in one batch call."""
+    import torch
+    import paper_1407_2343_amd as snlm
+    items = _ragged(8, 6, 30, 200)
+    ctx = _ctx(64 << 20)
+    jobs, outs, xs = [], [], []
+    params = [(5, 2, "box", "row_col"), (10, 3, "gauss", "col_row"), (15, 4, "box", "col_row"),
+              (10, 3, "box", "row_col")]
+    for i, (im, sig) in enumerate(items):
+        x = torch.from_numpy(im).to("cuda:0")
+        o = torch.empty_like(x)
+        S, K, kern, order = params[i % len(params)]
+        jobs.append(ctx.job_for(x, o, S, K, 10 * sig, kern, order))
+        xs.append((x, S, K, sig, kern, order))
+        outs.append(o)
+    ctx.ensure_arena(sum(snlm.workspace_bytes(*x.shape) for x, *_ in xs))
+    ctx.denoise_jobs(jobs, sync=True)
+    for (x, S, K, sig, kern, order), o in zip(xs, outs):
+        alone = ctx.denoise(x, S, K, 10 * sig, kern, order, sync=True)
+        assert torch.equal(o, alone)
+    ctx.close()
+
+
+def test_serving_alone_equals_mix():
+    import torch
+    import paper_1407_2343_amd as snlm
+    rng = np.random.default_rng(11)
+    arena = 24 << 20  # small enough that jobs queue for arena space
+    srv = _ctx(arena)
+    solo = _ctx(64 << 20)
+    reqs = []
+    for i in range(48):
+        H = int(np.exp(rng.uniform(np.log(40), np.log(700))))
+        W = int(np.exp(rng.uniform(np.log(40), np.log(700))))
+        sig = float(rng.uniform(10, 40))
+        S = int(rng.choice([5, 10, 15]))
+        K = int(rng.choice([2, 3, 4]))
+        kern = "gauss" if rng.random() < 0.5 else "box"
+        order = "col_row" if rng.random() < 0.5 else "row_col"
+        x = torch.from_numpy(noisy_image(H, W, sig, 500 + i)).to("cuda:0")
+        o = torch.full_like(x, -1.0)
+        reqs.append((x, o, S, K, 10 * sig, kern, order))
+    torch.cuda.synchronize()
+    tickets = []
+    for (x, o, S, K, h, kern, order) in reqs:
+        tickets.append(srv.submit(srv.job_for(x, o, S, K, h, kern, order)))
+        time.sleep(0.0005)
+    times = {}
+    pending = set(tickets)
+    t0 = time.time()
+    while pending and time.time() - t0 < 60:
+        for t in list(pending):
+            ts = srv.job_times(t)
+            if ts[2] > 0:
+                times[t] = ts
+                st = srv.poll(t)
+                assert st == snlm.OK, (t, st, srv.last_error())
+                pending.discard(t)
+        time.sleep(0.001)
+    assert not pending, "served jobs did not finish"
+    assert srv.poll(tickets[0]) == snlm.ENOTICKET
+    # results: bitwise equal to the same job run alone
+    for i, (x, o, S, K, h, kern, order) in enumerate(reqs):
+        alone = solo.denoise(x, S, K, h, kern, order, sync=True)
+        assert torch.equal(o, alone), i
+    # parity of a few served results
+    for (x, o, S, K, h, kern, order) in reqs[:3]:
+        ref = oracle.snlm(x.cpu().numpy().astype(np.float64), S, K, h, kern, order)
+        assert max_abs(o.cpu().numpy(), ref) <= TOL
+    # overlap: some job was admitted while an earlier-admitted one was still in flight
+    spans = sorted(times.values(), key=lambda v: v[1])
+    overlapped = any(spans[k][1] < spans[j][2] and spans[k][1] > spans[j][1]
+                     for j in range(len(spans)) for k in range(j + 1, len(spans)))
+    queued = sum(1 for v in spans if v[1] > v[0] + 50.0)
+    say("served", len(spans), "overlapped", overlapped, "queued", queued)
+    assert overlapped
+    srv.close()
+    solo.close()
+
+
+def test_serving_errors():
+    import torch
+    import paper_1407_2343_amd as snlm
+    srv = _ctx(1 << 20)
+    x = torch.zeros((600, 600), device="cuda:0")
+    o = torch.empty_like(x)
+    with pytest.raises(snlm.SnlmError) as e:
+        srv.submit(srv.job_for(x, o, 10, 3, 100.0))  # needs 1.4 MiB > 1 MiB arena
+    assert e.value.status == snlm.ENOMEM
+    assert srv.poll(12345) == snlm.ENOTICKET
+    small = torch.zeros((50, 60), device="cuda:0")
+    so = torch.empty_like(small)
+    t = srv.submit(srv.job_for(small, so, 5, 2, 100.0))
+    srv.close()  # drains in-flight work
+    assert float(so.abs().max()) == 0.0
+
+
+def _sample_pixels(H, W, n, seed):
+    rng = np.random.default_rng(seed)
+    pts = {(0, 0), (0, W - 1), (H - 1, 0), (H - 1, W - 1), (H // 2, 0), (0, W // 2)}
+    while len(pts) < n:
+        pts.add((int(rng.integers(0, H)), int(rng.integers(0, W))))
+    return sorted(pts)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+@pytest.mark.parametrize("sum", ["block", "plain", "kahan"])
+def test_precision_variants_large(dtype, sum):
+    """2048 x 2048, sigma 30, S=15, K=4, box: sampled pixels vs the oracle run
+    on exactly the values the GPU read."""
+    import torch
+    import paper_1407_2343_amd as snlm
+    H = W = 2048
+    img = noisy_image(H, W, 30.0, seed=3000)
+    x = torch.from_numpy(img.astype(np.float16 if dtype == "f16" else np.float32)).to("cuda:0")
+    ctx = _ctx(snlm.workspace_bytes(H, W) + (1 << 20))
+    say("precision", dtype, sum)
+    y = ctx.denoise(x, 15, 4, 300.0, "box", "row_col", sum=sum, sync=True).cpu().numpy()
+    xr = x.cpu().numpy().astype(np.float64)
+    worst = 0.0
+    for (r, c) in _sample_pixels(H, W, 48, 7):
+        ref = oracle.pixel(xr, r, c, 15, 4, 300.0, "box", "row_col")
+        worst = max(worst, abs(float(y[r, c]) - ref))
+    say("  sampled max-abs", worst)
+    assert worst <= TOL
+    ctx.close()
+
+
+def test_autotune_keeps_bits():
+    import torch
+    import paper_1407_2343_amd as snlm
+    img = noisy_image(700, 900, 20.0, seed=44)
+    x = torch.from_numpy(img).to("cuda:0")
+    ctx = _ctx(64 << 20)
+    before = ctx.denoise(x, 10, 3, 200.0, sync=True).clone()
+    best = ctx.autotune(x, 10, 3, 200.0)
+    say("autotune chose", best)
+    assert best > 0 and best % 16 == 0
+    after = ctx.denoise(x, 10, 3, 200.0, sync=True)
+    assert torch.equal(before, after)
+    ctx.close()
