@@ -244,6 +244,10 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-batch", action="store_true",
+                    help="only the batched steps (for rocprofv3 kernel traces and counters)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only a device-to-device copy of MIB MiB (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -256,6 +260,15 @@ def main():
 
     assert torch.cuda.is_available(), "no GPU"
     torch.cuda.set_device(0)
+    if a.calibrate_copy:
+        n = a.calibrate_copy << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n}), flush=True)
+        return
     log("generating the batch workload")
     items = batch_workload(64, 128, 1024, seed=2000)
     xs = [torch.from_numpy(img).to("cuda:0") for img, _ in items]
@@ -269,8 +282,14 @@ def main():
     def step():
         ctx.denoise_jobs(jobs)
 
+    log("autotuning the batched segment length")
+    seg = ctx.autotune_batch(jobs)
     log("batched: warmup + timed")
     ms_step, wall_ms = time_steps(torch, step, a.steps, a.warmup)
+    if a.profile_batch:
+        print(json.dumps({"batched_ms_per_step": round(ms_step, 4), "seg_len": seg}), flush=True)
+        ctx.close()
+        return
     # device time of the batched launches on the stream they run on
     ctx.timing_start()
     for _ in range(a.steps):
@@ -327,7 +346,8 @@ def main():
         "data": "synthetic (seeded shapes + gradient + texture + Gaussian noise)",
         "config": {"workload": "batched: 64 FP32 images, H,W log-uniform [128,1024], "
                                "sigma in {10,20,30,40}, h=10 sigma, S=10, K=3, box, row_col",
-                   "pixels_per_step": int(total_px), "images": len(xs)},
+                   "pixels_per_step": int(total_px), "images": len(xs),
+                   "autotuned_seg_len": seg},
         "plain_same_images_mpx": round(plain_batch_mpx, 1),
         "plain_512_mpx": plain512,
         "wall_ms_per_step": round(wall_ms, 4),

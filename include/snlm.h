@@ -98,10 +98,9 @@ typedef struct {
  *   stream       the caller's hipStream_t (NULL = legacy default stream);
  *                every call is ordered after work already queued on it, and
  *                work queued on it afterwards runs after the call's kernels
- *   arena        caller-owned device buffer for intermediates and, when
- *                serving, staged job images; may be NULL if arena_bytes = 0
- *                (then only S = 0 jobs and jobs of 1 pass can run -- in
- *                practice give an arena of snlm_workspace_bytes per job)
+ *   arena        caller-owned device buffer for the FP32 intermediates
+ *                (snlm_workspace_bytes per image); may be NULL only with
+ *                arena_bytes = 0, which then rejects every job (SNLM_ENOMEM)
  * Returns SNLM_OK and *ctx, SNLM_EINVAL for a NULL ctx or a bad device,
  * SNLM_EDEVICE if the HIP runtime fails. */
 int snlm_create(snlm_ctx **ctx, int device, void *stream, void *arena, size_t arena_bytes);
@@ -115,7 +114,8 @@ int snlm_destroy(snlm_ctx *ctx);
  * calls), rounded up to 256 bytes. */
 size_t snlm_workspace_bytes(int H, int W, snlm_dtype dtype);
 
-/* Arena bytes one served job needs: staged input, intermediate, output. */
+/* Arena bytes one served job holds while in flight (its FP32 intermediate;
+ * input and output stay in the caller's buffers). */
 size_t snlm_serving_bytes(int H, int W, snlm_dtype dtype);
 
 /* Separable NLM of one FP32 image with contiguous rows (ld = W).  Enqueued on
@@ -145,10 +145,11 @@ int snlm_sync(snlm_ctx *ctx);
 
 /* Serving.  Submits a job to the context's scheduler and returns at once with
  * a ticket.  The scheduler admits jobs in arrival order as arena space
- * (snlm_serving_bytes per job) frees up, stages the image into the arena,
- * runs admitted jobs in batched persistent launches that overlap on the
- * device with launches already running, and copies each result to job->out.
- * img and out must stay valid until snlm_poll returns non-PENDING.
+ * (snlm_serving_bytes per job: the HBM budget) frees up, runs each round of
+ * admitted jobs as batched persistent launches on one of several streams, so
+ * that a round overlaps on the device with rounds already running, and
+ * writes each result to job->out.  img and out must stay valid until
+ * snlm_poll returns non-PENDING.
  * Errors: SNLM_EINVAL, SNLM_ENOMEM (the job can never fit the arena),
  * SNLM_ECLOSED. */
 int snlm_submit(snlm_ctx *ctx, const snlm_job *job, uint64_t *ticket);
@@ -172,6 +173,12 @@ int snlm_validate(const snlm_job *job, const char **why);
  * as scratch input/output), and remembers it for later jobs with seg_len = 0
  * of the same (S, K, kernel, size class).  *best receives the choice. */
 int snlm_autotune(snlm_ctx *ctx, const snlm_job *probe, int *best);
+
+/* Selects the segment length of batched launches for the kernel classes of
+ * these jobs (timing each candidate on the jobs themselves; their outputs are
+ * overwritten) and remembers it for later batches of the same classes.
+ * Results do not depend on the choice.  *best receives it. */
+int snlm_autotune_batch(snlm_ctx *ctx, const snlm_job *jobs, int n, int *best);
 
 /* Saves / loads the autotuner's choices as a small JSON file. */
 int snlm_autotune_save(snlm_ctx *ctx, const char *path);

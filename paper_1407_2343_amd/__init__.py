@@ -81,6 +81,8 @@ def lib():
             L.snlm_job_times.argtypes = [vp, ctypes.c_uint64] + [ctypes.POINTER(ctypes.c_double)] * 3
             L.snlm_validate.argtypes = [jp, ctypes.POINTER(ctypes.c_char_p)]
             L.snlm_autotune.argtypes = [vp, jp, ctypes.POINTER(i)]
+            L.snlm_autotune_batch.argtypes = [vp, jp, i, ctypes.POINTER(i)]
+            L.snlm_autotune_batch.restype = ctypes.c_int
             L.snlm_autotune_save.argtypes = [vp, ctypes.c_char_p]
             L.snlm_autotune_load.argtypes = [vp, ctypes.c_char_p]
             L.snlm_plan_seg_len.argtypes = [vp, jp, i]
@@ -264,6 +266,14 @@ class Context:
         best = ctypes.c_int()
         self.check(lib().snlm_autotune(self._ptr, ctypes.byref(job), ctypes.byref(best)),
                    "snlm_autotune")
+        return best.value
+
+    def autotune_batch(self, jobs) -> int:
+        """Pick the batched segment length for the classes of these jobs."""
+        arr = jobs if isinstance(jobs, ctypes.Array) else job_array(jobs)
+        best = ctypes.c_int()
+        self.check(lib().snlm_autotune_batch(self._ptr, arr, len(arr), ctypes.byref(best)),
+                   "snlm_autotune_batch")
         return best.value
 
     def plan_seg_len(self, job: Job, pass_: int) -> int:

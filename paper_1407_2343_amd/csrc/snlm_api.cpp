@@ -320,6 +320,7 @@ struct snlm_ctx {
     std::vector<LaunchSlot> slots;
     std::map<TuneKey, int> tuned;
     std::mutex tune_mu;
+    std::map<ClassKey, int> batch_tuned;  // batched segment length per kernel class
     int tune_epoch = 0;  // bumped whenever tuned changes (invalidates cached batch plans)
     // Batched launches: split (default) runs all first-pass tiles, then all
     // second-pass tiles, as two persistent launches in one graph; fused
@@ -464,45 +465,80 @@ struct ClassPlan {
     int ntiles_first = 0;
 };
 
-// Groups jobs by kernel variant and lays out their tiles: every first-pass
-// tile of the class, then every second-pass tile, both in job order.
+// Segment length shared by the lines of every image of one batched pass: a
+// fixed length (rather than a fixed number of segments per line) keeps the
+// tiles of all images about the same size, so that with the longest-first
+// order below the persistent workgroups finish together.  Aims at about two
+// tiles per SIMD.
+int batch_seg_len(snlm_ctx* c, const std::vector<const snlm_job*>& jobs, int pass) {
+    double chunks = 0;
+    for (auto* j : jobs) {
+        const bool rows = pass_rows(*j, pass);
+        const int n = rows ? j->W : j->H;
+        chunks += (double)groups_of(*j, pass) * ((n + kChunk - 1) / kChunk);
+    }
+    {
+        std::lock_guard<std::mutex> g(c->tune_mu);
+        auto it = c->batch_tuned.find(class_of(*jobs[0]));
+        if (it != c->batch_tuned.end()) return it->second;
+    }
+    const double target = 2.0 * 4 * std::max(c->num_cu, 1);
+    return kChunk * std::max(1, (int)std::lround(chunks / target));
+}
+
+// Groups jobs by kernel class and lays out their tiles: every first-pass tile
+// of the class, then every second-pass tile, each pass ordered by decreasing
+// tile length (an LPT order for the claiming workgroups).
 void plan_classes(snlm_ctx* c, const std::vector<const snlm_job*>& jobs,
                   const std::vector<char*>& mids, std::vector<ClassPlan>& out) {
     std::map<ClassKey, size_t> idx;
-    std::map<ClassKey, int> groups[2];
-    for (size_t i = 0; i < jobs.size(); ++i)
-        for (int p = 0; p < 2; ++p) groups[p][class_of(*jobs[i])] += groups_of(*jobs[i], p);
+    std::map<ClassKey, std::vector<const snlm_job*>> members;
+    for (auto* j : jobs) members[class_of(*j)].push_back(j);
+    std::map<ClassKey, int> seg[2];
+    for (auto& kv : members)
+        for (int p = 0; p < 2; ++p) seg[p][kv.first] = batch_seg_len(c, kv.second, p);
     for (size_t i = 0; i < jobs.size(); ++i) {
-        const ClassKey fn = class_of(*jobs[i]);
-        auto it = idx.find(fn);
+        const ClassKey key = class_of(*jobs[i]);
+        auto it = idx.find(key);
         if (it == idx.end()) {
-            idx[fn] = out.size();
+            idx[key] = out.size();
             out.emplace_back();
             out.back().fn[0] = kernel_fn(*jobs[i], 0);
             out.back().fn[1] = kernel_fn(*jobs[i], 1);
-            it = idx.find(fn);
+            it = idx.find(key);
         }
         ClassPlan& cp = out[it->second];
         BatchJob bj;
         std::memset(&bj, 0, sizeof(bj));
         for (int p = 0; p < 2; ++p) {
-            fill_pass(bj.pass[p], *jobs[i], p, mids[i], chosen_seg_len(c, *jobs[i], p, groups[p][fn]));
+            const int L = jobs[i]->seg_len > 0 ? jobs[i]->seg_len : seg[p][key];
+            fill_pass(bj.pass[p], *jobs[i], p, mids[i], L);
             bj.tiles[p] = bj.pass[p].ngroups * bj.pass[p].nseg;
         }
         cp.jobs.push_back(bj);
     }
     for (auto& cp : out) {
-        int t = 0;
-        for (size_t j = 0; j < cp.jobs.size(); ++j) {
-            cp.jobs[j].tile_base[0] = t;
-            for (int k = 0; k < cp.jobs[j].tiles[0]; ++k) cp.tile_job.push_back((uint32_t)j);
-            t += cp.jobs[j].tiles[0];
-        }
-        cp.ntiles_first = t;
-        for (size_t j = 0; j < cp.jobs.size(); ++j) {
-            cp.jobs[j].tile_base[1] = t;
-            for (int k = 0; k < cp.jobs[j].tiles[1]; ++k) cp.tile_job.push_back((uint32_t)j);
-            t += cp.jobs[j].tiles[1];
+        for (int p = 0; p < 2; ++p) {
+            struct T {
+                int work;
+                uint32_t job, tile;
+            };
+            std::vector<T> ts;
+            for (size_t j = 0; j < cp.jobs.size(); ++j) {
+                const PassDesc& d = cp.jobs[j].pass[p];
+                for (int t = 0; t < cp.jobs[j].tiles[p]; ++t) {
+                    const int sgi = t / d.ngroups;
+                    const int len = std::min(d.seg_len, d.n - sgi * d.seg_len);
+                    // a segment costs its chunks plus about half a chunk of pre-chunk
+                    ts.push_back({2 * ((len + kChunk - 1) / kChunk) + 1, (uint32_t)j, (uint32_t)t});
+                }
+            }
+            std::stable_sort(ts.begin(), ts.end(), [](const T& a, const T& b) { return a.work > b.work; });
+            for (auto& t : ts) {
+                cp.tile_job.push_back(t.job);
+                cp.tile_job.push_back(t.tile);
+            }
+            if (p == 0) cp.ntiles_first = (int)ts.size();
         }
     }
 }
@@ -557,7 +593,7 @@ int upload_class(snlm_ctx* c, LaunchSlot& s, const ClassPlan& cp, hipStream_t st
     BatchHeader hdr;
     hdr.njobs = (int)cp.jobs.size();
     hdr.ntiles_first = cp.ntiles_first;
-    hdr.ntiles = (int)cp.tile_job.size();
+    hdr.ntiles = (int)(cp.tile_job.size() / 2);
     hdr.spin_limit = kSpinLimit;
     std::memcpy(s.h_tab, &hdr, sizeof(hdr));
     std::memcpy(s.h_tab + off_jobs, cp.jobs.data(), cp.jobs.size() * sizeof(BatchJob));
@@ -1079,6 +1115,49 @@ int snlm_autotune(snlm_ctx* c, const snlm_job* probe, int* best) {
     return SNLM_OK;
 }
 
+int snlm_autotune_batch(snlm_ctx* c, const snlm_job* jobs, int n, int* best) {
+    if (!c) return SNLM_EINVAL;
+    if (!jobs || n < 1) return fail(c, SNLM_EINVAL, "need at least one job");
+    static const int cand[] = {32, 48, 64, 96, 128, 160, 192, 256};
+    std::vector<snlm_job> js(jobs, jobs + n);
+    hipEvent_t e0, e1;
+    HIP_CHECK(c, hipSetDevice(c->device));
+    HIP_CHECK(c, hipEventCreate(&e0));
+    HIP_CHECK(c, hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    int choice = 0;
+    for (int L : cand) {
+        for (auto& j : js) j.seg_len = L;
+        float total = 0.0f;
+        for (int rep = 0; rep < 4; ++rep) {
+            int rc = snlm_denoise_batch(c, js.data(), n);
+            if (rc) return rc;
+            HIP_CHECK(c, hipEventRecord(e0, c->user));
+            rc = snlm_denoise_batch(c, js.data(), n);
+            if (rc) return rc;
+            HIP_CHECK(c, hipEventRecord(e1, c->user));
+            HIP_CHECK(c, hipEventSynchronize(e1));
+            float ms = 0.0f;
+            HIP_CHECK(c, hipEventElapsedTime(&ms, e0, e1));
+            if (rep > 0) total += ms;
+        }
+        if (total < best_ms) {
+            best_ms = total;
+            choice = L;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    {
+        std::lock_guard<std::mutex> g(c->tune_mu);
+        for (auto& j : js) c->batch_tuned[class_of(j)] = choice;
+        ++c->tune_epoch;
+    }
+    c->last_batch_classes = 0;
+    if (best) *best = choice;
+    return snlm_sync(c);
+}
+
 int snlm_autotune_save(snlm_ctx* c, const char* path) {
     if (!c || !path) return SNLM_EINVAL;
     FILE* f = std::fopen(path, "w");
@@ -1090,6 +1169,13 @@ int snlm_autotune_save(snlm_ctx* c, const char* path) {
         std::fprintf(f, "%s\n  {\"S\": %d, \"K\": %d, \"variant\": %d, \"n_class\": %d, \"lines_class\": %d, \"seg_len\": %d}",
                      first ? "" : ",", kv.first.S, kv.first.K, kv.first.var, kv.first.nclass,
                      kv.first.lclass, kv.second);
+        first = false;
+    }
+    std::fprintf(f, "\n], \"batch\": [");
+    first = true;
+    for (auto& kv : c->batch_tuned) {
+        std::fprintf(f, "%s\n  {\"bS\": %d, \"K\": %d, \"variant\": %d, \"order\": %d, \"seg_len\": %d}",
+                     first ? "" : ",", kv.first.S, kv.first.K, kv.first.var, kv.first.order, kv.second);
         first = false;
     }
     std::fprintf(f, "\n]}\n");
@@ -1121,6 +1207,20 @@ int snlm_autotune_load(snlm_ctx* c, const char* path) {
             ++loaded;
         }
         pos += 5;
+    }
+    pos = 0;
+    while ((pos = text.find("{\"bS\":", pos)) != std::string::npos) {
+        ClassKey k;
+        int seg = 0;
+        if (std::sscanf(text.c_str() + pos,
+                        "{\"bS\": %d, \"K\": %d, \"variant\": %d, \"order\": %d, \"seg_len\": %d}",
+                        &k.S, &k.K, &k.var, &k.order, &seg) == 5 &&
+            seg > 0 && seg % kChunk == 0) {
+            c->batch_tuned[k] = seg;
+            ++c->tune_epoch;
+            ++loaded;
+        }
+        pos += 6;
     }
     return loaded > 0 ? SNLM_OK : fail(c, SNLM_EINVAL, "no entries");
 }

@@ -63,12 +63,12 @@ struct PassDesc {
     float taps[kMaxK + 1]; // Gaussian taps g(0..K) (g(0) = 1)
 };
 
-// A batch: jobs, each with two passes, and a flat list of tiles.  Tiles of
-// every first pass come before tiles of any second pass.
+// A batch: jobs, each with two passes, and a flat list of tiles (job, tile of
+// that job's pass).  Tiles of every first pass come before tiles of any
+// second pass; within a pass the host orders them longest first.
 struct BatchJob {
     PassDesc pass[2];
     int32_t tiles[2];      // tiles per pass (ngroups * nseg)
-    int32_t tile_base[2];  // index of the pass's first tile in the flat list
 };
 
 struct BatchHeader {
@@ -85,7 +85,7 @@ struct KernelArgs {
     PassDesc direct;
     const BatchHeader* hdr;
     const BatchJob* jobs;
-    const uint32_t* tile_job;  // tile -> job index
+    const uint32_t* tile_job;  // tile t -> job tile_job[2 t], its tile tile_job[2 t + 1]
     uint32_t* counters;        // [1 + j] finished first-pass tiles of job j
     uint32_t* claim;           // claim counter of this launch
     uint32_t* status;          // set non-zero when a dependency wait gives up
@@ -520,8 +520,8 @@ __global__ __launch_bounds__(kLanes) void snlm_kernel(KernelArgs args) {
             __syncthreads();
             if (t >= (uint32_t)args.tile_hi) break;
             pass = t < (uint32_t)hdr.ntiles_first ? 0 : 1;
-            job = (int)__builtin_amdgcn_readfirstlane(args.tile_job[t]);
-            tile = (int)t - (int)__builtin_amdgcn_readfirstlane(args.jobs[job].tile_base[pass]);
+            job = (int)__builtin_amdgcn_readfirstlane(args.tile_job[2 * t]);
+            tile = (int)__builtin_amdgcn_readfirstlane(args.tile_job[2 * t + 1]);
             if (pass == 1 && args.wait) {
                 // Wait until every first-pass tile of this job has been written:
                 // poll with relaxed device-scope loads (no cache invalidation per

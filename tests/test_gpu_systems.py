@@ -98,7 +98,7 @@ def test_serving_alone_equals_mix():
     import torch
     import paper_1407_2343_amd as snlm
     rng = np.random.default_rng(11)
-    arena = 24 << 20  # small enough that jobs queue for arena space
+    arena = 6 << 20  # small enough that jobs queue for arena space
     srv = _ctx(arena)
     solo = _ctx(64 << 20)
     reqs = []
@@ -115,9 +115,9 @@ def test_serving_alone_equals_mix():
         reqs.append((x, o, S, K, 10 * sig, kern, order))
     torch.cuda.synchronize()
     tickets = []
-    for (x, o, S, K, h, kern, order) in reqs:
-        tickets.append(srv.submit(srv.job_for(x, o, S, K, h, kern, order)))
-        time.sleep(0.0005)
+    jobs = [srv.job_for(x, o, S, K, h, kern, order) for (x, o, S, K, h, kern, order) in reqs]
+    for j in jobs:  # a burst: later jobs arrive while earlier ones run
+        tickets.append(srv.submit(j))
     times = {}
     pending = set(tickets)
     t0 = time.time()
@@ -147,6 +147,7 @@ def test_serving_alone_equals_mix():
     queued = sum(1 for v in spans if v[1] > v[0] + 50.0)
     say("served", len(spans), "overlapped", overlapped, "queued", queued)
     assert overlapped
+    assert queued > 0
     srv.close()
     solo.close()
 
@@ -211,4 +212,30 @@ def test_autotune_keeps_bits():
     assert best > 0 and best % 16 == 0
     after = ctx.denoise(x, 10, 3, 200.0, sync=True)
     assert torch.equal(before, after)
+    ctx.close()
+
+
+def test_batch_autotune_and_tuning_file(tmp_path):
+    import torch
+    import paper_1407_2343_amd as snlm
+    items = _ragged(6, 9)
+    ctx = _ctx(64 << 20)
+    xs = [torch.from_numpy(im).to("cuda:0") for im, _ in items]
+    outs = [torch.empty_like(x) for x in xs]
+    jobs = [ctx.job_for(x, o, 10, 3, 10 * s) for x, o, (_, s) in zip(xs, outs, items)]
+    before = None
+    ctx.denoise_jobs(jobs, sync=True)
+    before = [o.clone() for o in outs]
+    best = ctx.autotune_batch(jobs)
+    assert best % 16 == 0 and best > 0
+    ctx.denoise_jobs(jobs, sync=True)
+    for a, b in zip(before, outs):
+        assert torch.equal(a, b)
+    path = str(tmp_path / "tune.json")
+    ctx.save_tuning(path)
+    text = open(path).read()
+    assert '"batch"' in text and str(best) in text
+    other = _ctx(64 << 20)
+    other.load_tuning(path)
+    other.close()
     ctx.close()
