@@ -287,7 +287,7 @@ def main():
     log("batched: warmup + timed")
     ms_step, wall_ms = time_steps(torch, step, a.steps, a.warmup)
     if a.profile_batch:
-        print(json.dumps({"batched_ms_per_step": round(ms_step, 4), "seg_len": seg}), flush=True)
+        print(json.dumps({"batched_ms_per_step": round(ms_step, 4), "waves_per_simd": seg}), flush=True)
         ctx.close()
         return
     # device time of the batched launches on the stream they run on
@@ -347,7 +347,7 @@ def main():
         "config": {"workload": "batched: 64 FP32 images, H,W log-uniform [128,1024], "
                                "sigma in {10,20,30,40}, h=10 sigma, S=10, K=3, box, row_col",
                    "pixels_per_step": int(total_px), "images": len(xs),
-                   "autotuned_seg_len": seg},
+                   "autotuned_waves_per_simd": seg},
         "plain_same_images_mpx": round(plain_batch_mpx, 1),
         "plain_512_mpx": plain512,
         "wall_ms_per_step": round(wall_ms, 4),

@@ -129,14 +129,18 @@ int snlm_denoise(snlm_ctx *ctx, const void *img, float *out, int H, int W, int S
 /* As snlm_denoise with every option of snlm_job. */
 int snlm_denoise_ex(snlm_ctx *ctx, const snlm_job *job);
 
-/* Many images in one persistent launch per (S, K, kernel) class: each launch
- * is captured once in a HIP graph (counter reset + persistent kernel) and
- * replayed; its workgroups claim row tiles of every image, then column tiles,
- * a column tile waiting only for the first-pass tiles of its own image.  The
- * arena must hold the sum of the jobs' snlm_workspace_bytes.  Enqueued on the
- * context stream.  Results are bitwise identical to snlm_denoise_ex of each
- * job.  Errors as snlm_denoise_ex, plus SNLM_EINVAL for n < 1 and SNLM_ENOMEM
- * when the jobs do not fit the arena together. */
+/* Many images in two persistent launches per (S, K, kernel, order) class,
+ * captured once in a HIP graph (counter reset + first-pass launch +
+ * second-pass launch) and replayed.  The line groups of every image of a pass
+ * are cut at 16-sample boundaries into one equal share of work per persistent
+ * workgroup (jobs with seg_len > 0, and box jobs with plain or Kahan sums,
+ * keep their segments whole).  The arena must hold the sum of the jobs'
+ * snlm_workspace_bytes.  Enqueued on the context stream.  Results are bitwise
+ * identical to snlm_denoise_ex of each job.  Errors as snlm_denoise_ex, plus
+ * SNLM_EINVAL for n < 1 and SNLM_ENOMEM when the jobs do not fit the arena
+ * together.  With the environment variable SNLM_BATCH_MODE=fused at context
+ * creation, a single launch per class instead claims tiles with an atomic
+ * counter, second-pass tiles waiting for the first-pass tiles of their image. */
 int snlm_denoise_batch(snlm_ctx *ctx, const snlm_job *jobs, int n);
 
 /* Waits for everything enqueued on the context stream by this library and
@@ -174,10 +178,11 @@ int snlm_validate(const snlm_job *job, const char **why);
  * of the same (S, K, kernel, size class).  *best receives the choice. */
 int snlm_autotune(snlm_ctx *ctx, const snlm_job *probe, int *best);
 
-/* Selects the segment length of batched launches for the kernel classes of
- * these jobs (timing each candidate on the jobs themselves; their outputs are
- * overwritten) and remembers it for later batches of the same classes.
- * Results do not depend on the choice.  *best receives it. */
+/* Selects the number of persistent waves per SIMD (1..4, within the kernel's
+ * occupancy) of batched launches for the kernel classes of these jobs, timing
+ * each candidate on the jobs themselves (their outputs are overwritten), and
+ * remembers it for later batches of the same classes.  Results do not depend
+ * on the choice.  *best receives it. */
 int snlm_autotune_batch(snlm_ctx *ctx, const snlm_job *jobs, int n, int *best);
 
 /* Saves / loads the autotuner's choices as a small JSON file. */

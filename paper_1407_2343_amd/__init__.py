@@ -269,7 +269,7 @@ class Context:
         return best.value
 
     def autotune_batch(self, jobs) -> int:
-        """Pick the batched segment length for the classes of these jobs."""
+        """Pick the persistent waves per SIMD of batched launches for the classes of these jobs."""
         arr = jobs if isinstance(jobs, ctypes.Array) else job_array(jobs)
         best = ctypes.c_int()
         self.check(lib().snlm_autotune_batch(self._ptr, arr, len(arr), ctypes.byref(best)),

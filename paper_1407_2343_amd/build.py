@@ -5,7 +5,7 @@ unit (snlm_inst.hip compiled with -DSNLM_S=<S>), so the 17 units compile in
 parallel; the host library (snlm_api.cpp) is compiled with hipcc and the whole
 is linked into paper_1407_2343_amd/libsnlm.so.
 
-    python -m paper_1407_2343_amd.build [--jobs N] [--only-s 5,10,15]
+    python -m paper_1407_2343_amd.build [--jobs N] [--only-s 5,10,15] [--incremental]
 
 ``--only-s`` restricts the compiled S values (the others are then missing from
 the library and rejected at run time); it is for quick development builds.
@@ -44,14 +44,26 @@ def _run(cmd):
     return time.time() - t0, out
 
 
-def build(jobs: int | None = None, only_s=None, verbose: bool = False) -> str:
+def _fresh(obj, deps):
+    """True when obj exists and is newer than every dependency."""
+    if not os.path.exists(obj):
+        return False
+    t = os.path.getmtime(obj)
+    return all(os.path.getmtime(d) < t for d in deps)
+
+
+def build(jobs: int | None = None, only_s=None, verbose: bool = False, incremental: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or int(os.environ.get("SNLM_BUILD_JOBS", "0")) or max(1, os.cpu_count() or 1)
     s_values = list(range(0, 17)) if only_s is None else sorted(set([0] + list(only_s)))
     objs, cmds = [], []
+    dev_deps = [os.path.join(CSRC, f) for f in ("snlm_inst.hip", "snlm_device.hpp", "snlm_registry.hpp")]
+    dev_deps.append(os.path.join(ROOT, "include", "snlm.h"))
     for s in s_values:
         o = os.path.join(BUILD, "snlm_inst_s%d.o" % s)
         objs.append(o)
+        if incremental and _fresh(o, dev_deps + [os.path.abspath(__file__)]):
+            continue
         cmds.append(COMMON + DEVICE_FLAGS + ["-DSNLM_S=%d" % s, "-c",
                                             os.path.join(CSRC, "snlm_inst.hip"), "-o", o])
     api_o = os.path.join(BUILD, "snlm_api.o")
@@ -90,9 +102,11 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
     ap.add_argument("--only-s", type=str, default=None)
+    ap.add_argument("--incremental", action="store_true",
+                    help="reuse kernel objects newer than the kernel sources")
     a = ap.parse_args(argv)
     only = [int(v) for v in a.only_s.split(",")] if a.only_s else None
-    build(a.jobs, only, verbose=True)
+    build(a.jobs, only, verbose=True, incremental=a.incremental)
 
 
 if __name__ == "__main__":

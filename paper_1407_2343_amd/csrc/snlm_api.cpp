@@ -25,6 +25,7 @@
 
 using snlm::BatchHeader;
 using snlm::BatchJob;
+using snlm::BatchTile;
 using snlm::KernelArgs;
 using snlm::PassDesc;
 
@@ -276,7 +277,8 @@ struct LaunchSlot {
     const void* fn2 = nullptr;    // second-pass kernel
     const void* fn_rows = nullptr;  // row-pass variant (handles both passes; fused mode)
     int njobs = 0, ntiles = 0, ntiles_first = 0;
-    size_t off_jobs = 0, off_tiles = 0;
+    int workers[2] = {0, 0};  // static workgroups of each pass (split launches)
+    size_t off_jobs = 0, off_tiles = 0, off_first[2] = {0, 0};
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     const void* g_fn = nullptr;
@@ -320,7 +322,7 @@ struct snlm_ctx {
     std::vector<LaunchSlot> slots;
     std::map<TuneKey, int> tuned;
     std::mutex tune_mu;
-    std::map<ClassKey, int> batch_tuned;  // batched segment length per kernel class
+    std::map<ClassKey, int> batch_tuned;  // waves per SIMD of the batched launches of a kernel class
     int tune_epoch = 0;  // bumped whenever tuned changes (invalidates cached batch plans)
     // Batched launches: split (default) runs all first-pass tiles, then all
     // second-pass tiles, as two persistent launches in one graph; fused
@@ -394,12 +396,6 @@ int chosen_seg_len(snlm_ctx* c, const snlm_job& j, int pass, int shared_groups =
     return heuristic_seg_len(groups, n, target);
 }
 
-int groups_of(const snlm_job& j, int pass) {
-    const bool rows = (pass == 0) == (j.order == SNLM_ROW_COL);
-    const int nlines = rows ? j.H : j.W;
-    return (nlines + snlm::kLanes - 1) / snlm::kLanes;
-}
-
 int timing_pair(snlm_ctx* c, std::pair<hipEvent_t, hipEvent_t>* p) {
     if (!c->t_pool.empty()) {
         *p = c->t_pool.back();
@@ -461,47 +457,139 @@ int fence_out(snlm_ctx* c, hipStream_t from) {
 struct ClassPlan {
     const void* fn[2] = {nullptr, nullptr};  // first-pass and second-pass kernels
     std::vector<BatchJob> jobs;
-    std::vector<uint32_t> tile_job;
+    std::vector<uint8_t> cut;        // per job: its lines may be cut anywhere on chunk boundaries
+    std::vector<BatchTile> tiles;   // first-pass tiles, then second-pass tiles
+    std::vector<uint32_t> first[2];  // per pass: workgroup k runs tiles first[k] .. first[k+1]-1
     int ntiles_first = 0;
 };
 
-// Segment length shared by the lines of every image of one batched pass: a
-// fixed length (rather than a fixed number of segments per line) keeps the
-// tiles of all images about the same size, so that with the longest-first
-// order below the persistent workgroups finish together.  Aims at about two
-// tiles per SIMD.
-int batch_seg_len(snlm_ctx* c, const std::vector<const snlm_job*>& jobs, int pass) {
-    double chunks = 0;
-    for (auto* j : jobs) {
-        const bool rows = pass_rows(*j, pass);
-        const int n = rows ? j->W : j->H;
-        chunks += (double)groups_of(*j, pass) * ((n + kChunk - 1) / kChunk);
+// Cost model of a tile, in units of one 16-sample chunk of one 64-line group:
+// a segment pays its chunks plus the pre-chunk that sets up its running sums
+// and sample window.
+constexpr double kSegOverhead = 1.25;
+constexpr int kMinPiece = 2;  // a cut leaves at least this many chunks on each side
+
+// A run of chunks [c0, c1) of one line group, cut freely at chunk boundaries
+// (block-restarted or Gaussian passes) or kept whole (a fixed segment).
+struct PieceSrc {
+    uint32_t job;
+    int group, n;  // n: line length in samples
+    int c0, c1;
+    bool cut;
+};
+
+// Greedy fill of workers with a cost budget W each, in source order: a
+// source that does not fit in what is left of the current worker is cut at
+// the chunk where the budget ends.  Returns the number of workers used; with
+// out/first non-null emits the tiles and the index of each worker's first tile.
+int fill_workers(const std::vector<PieceSrc>& src, double W, std::vector<BatchTile>* out,
+                 std::vector<uint32_t>* first) {
+    int workers = 1;
+    double cur = 0.0;
+    if (first) first->push_back((uint32_t)out->size());
+    auto next_worker = [&]() {
+        ++workers;
+        cur = 0.0;
+        if (first) first->push_back((uint32_t)out->size());
+    };
+    auto emit = [&](const PieceSrc& p, int a, int b) {
+        if (out) out->push_back({p.job, p.group, a * kChunk, std::min(b * kChunk, p.n)});
+        cur += (b - a) + kSegOverhead;
+    };
+    for (const PieceSrc& p : src) {
+        int pos = p.c0;
+        while (pos < p.c1) {
+            const int r = p.c1 - pos;
+            const double rem = W - cur;
+            if (r + kSegOverhead <= rem + 1e-9) {
+                emit(p, pos, p.c1);
+                pos = p.c1;
+                continue;
+            }
+            if (p.cut) {
+                const int k = std::min((int)std::floor(rem - kSegOverhead), r - kMinPiece);
+                if (k >= kMinPiece) {
+                    emit(p, pos, pos + k);
+                    pos += k;
+                    next_worker();
+                    continue;
+                }
+            }
+            if (cur > 0.0) {
+                next_worker();
+                continue;
+            }
+            // a fresh worker that cannot hold a good piece: overfill it
+            int k = r;
+            if (p.cut && r >= 2 * kMinPiece)
+                k = std::max(kMinPiece, std::min((int)std::floor(W - kSegOverhead), r - kMinPiece));
+            emit(p, pos, pos + k);
+            pos += k;
+            if (pos < p.c1) next_worker();
+        }
     }
-    {
-        std::lock_guard<std::mutex> g(c->tune_mu);
-        auto it = c->batch_tuned.find(class_of(*jobs[0]));
-        if (it != c->batch_tuned.end()) return it->second;
-    }
-    const double target = 2.0 * 4 * std::max(c->num_cu, 1);
-    return kChunk * std::max(1, (int)std::lround(chunks / target));
+    return workers;
 }
 
-// Groups jobs by kernel class and lays out their tiles: every first-pass tile
-// of the class, then every second-pass tile, each pass ordered by decreasing
-// tile length (an LPT order for the claiming workgroups).
+// Splits one pass of a class into P equal shares: the smallest per-worker
+// budget (bisection) with which the greedy fill needs at most P workers.
+// Workers past the last used one get empty ranges, so the grid is always P.
+void balance_pass(const std::vector<PieceSrc>& src, int P, std::vector<BatchTile>& tiles,
+                  std::vector<uint32_t>& first) {
+    double total = 0.0, biggest = 0.0;
+    for (const PieceSrc& p : src) {
+        const double w = (p.c1 - p.c0) + kSegOverhead;
+        total += w;
+        if (!p.cut) biggest = std::max(biggest, w);
+    }
+    double lo = std::max(total / P, biggest), hi = total + kSegOverhead;
+    if (fill_workers(src, lo, nullptr, nullptr) > P) {
+        for (int it = 0; it < 40 && hi - lo > 0.25; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (fill_workers(src, mid, nullptr, nullptr) <= P)
+                hi = mid;
+            else
+                lo = mid;
+        }
+    } else {
+        hi = lo;
+    }
+    first.clear();
+    fill_workers(src, hi, &tiles, &first);
+    while ((int)first.size() < P + 1) first.push_back((uint32_t)tiles.size());
+    first.resize(P + 1);
+    first[P] = (uint32_t)tiles.size();
+}
+
+// Waves per SIMD of the persistent launches of a class (autotuned, default 1:
+// one wave per SIMD already keeps the VALU busy when the work is balanced).
+int batch_waves(snlm_ctx* c, const ClassKey& key) {
+    std::lock_guard<std::mutex> g(c->tune_mu);
+    auto it = c->batch_tuned.find(key);
+    return it != c->batch_tuned.end() ? it->second : 1;
+}
+
+int batch_workers(snlm_ctx* c, const void* fn, int waves_per_simd) {
+    return std::max(1, std::min(occupancy_grid(c, fn), waves_per_simd * 4 * std::max(c->num_cu, 1)));
+}
+
+// Groups jobs by kernel class and lays out each pass of a class as P equal
+// shares, one per persistent workgroup (a static stream-K style split: the
+// line groups of every image of the pass are concatenated and cut at chunk
+// boundaries, so that a share may end inside one line group and the next
+// share continues it).  Passes that must keep whole lines (plain and Kahan
+// running sums) and jobs with an explicit segment length contribute fixed
+// segments that are never cut.
 void plan_classes(snlm_ctx* c, const std::vector<const snlm_job*>& jobs,
                   const std::vector<char*>& mids, std::vector<ClassPlan>& out) {
     std::map<ClassKey, size_t> idx;
-    std::map<ClassKey, std::vector<const snlm_job*>> members;
-    for (auto* j : jobs) members[class_of(*j)].push_back(j);
-    std::map<ClassKey, int> seg[2];
-    for (auto& kv : members)
-        for (int p = 0; p < 2; ++p) seg[p][kv.first] = batch_seg_len(c, kv.second, p);
+    std::vector<ClassKey> keys;
     for (size_t i = 0; i < jobs.size(); ++i) {
         const ClassKey key = class_of(*jobs[i]);
         auto it = idx.find(key);
         if (it == idx.end()) {
             idx[key] = out.size();
+            keys.push_back(key);
             out.emplace_back();
             out.back().fn[0] = kernel_fn(*jobs[i], 0);
             out.back().fn[1] = kernel_fn(*jobs[i], 1);
@@ -511,34 +599,38 @@ void plan_classes(snlm_ctx* c, const std::vector<const snlm_job*>& jobs,
         BatchJob bj;
         std::memset(&bj, 0, sizeof(bj));
         for (int p = 0; p < 2; ++p) {
-            const int L = jobs[i]->seg_len > 0 ? jobs[i]->seg_len : seg[p][key];
+            const int L = jobs[i]->seg_len > 0 ? jobs[i]->seg_len : (1 << 30);
             fill_pass(bj.pass[p], *jobs[i], p, mids[i], L);
-            bj.tiles[p] = bj.pass[p].ngroups * bj.pass[p].nseg;
         }
         cp.jobs.push_back(bj);
+        const bool whole_line = jobs[i]->kernel == SNLM_BOX && jobs[i]->sum != SNLM_SUM_BLOCK;
+        cp.cut.push_back(jobs[i]->seg_len <= 0 && !whole_line);
     }
-    for (auto& cp : out) {
+    for (size_t ci = 0; ci < out.size(); ++ci) {
+        ClassPlan& cp = out[ci];
+        const int waves = batch_waves(c, keys[ci]);
         for (int p = 0; p < 2; ++p) {
-            struct T {
-                int work;
-                uint32_t job, tile;
-            };
-            std::vector<T> ts;
+            std::vector<PieceSrc> src;
             for (size_t j = 0; j < cp.jobs.size(); ++j) {
                 const PassDesc& d = cp.jobs[j].pass[p];
-                for (int t = 0; t < cp.jobs[j].tiles[p]; ++t) {
-                    const int sgi = t / d.ngroups;
-                    const int len = std::min(d.seg_len, d.n - sgi * d.seg_len);
-                    // a segment costs its chunks plus about half a chunk of pre-chunk
-                    ts.push_back({2 * ((len + kChunk - 1) / kChunk) + 1, (uint32_t)j, (uint32_t)t});
-                }
+                const int nch = (d.n + kChunk - 1) / kChunk;
+                const bool fixed = !cp.cut[j];
+                const int step = fixed ? d.seg_len / kChunk : nch;
+                for (int g = 0; g < d.ngroups; ++g)
+                    for (int c0 = 0; c0 < nch; c0 += step)
+                        src.push_back({(uint32_t)j, g, d.n, c0, std::min(c0 + step, nch), !fixed});
             }
-            std::stable_sort(ts.begin(), ts.end(), [](const T& a, const T& b) { return a.work > b.work; });
-            for (auto& t : ts) {
-                cp.tile_job.push_back(t.job);
-                cp.tile_job.push_back(t.tile);
-            }
-            if (p == 0) cp.ntiles_first = (int)ts.size();
+            const size_t before = cp.tiles.size();
+            std::vector<BatchTile> tiles;
+            balance_pass(src, batch_workers(c, cp.fn[p], waves), tiles, cp.first[p]);
+            for (auto& f : cp.first[p]) f += (uint32_t)before;
+            for (const BatchTile& t : tiles) cp.jobs[t.job].tiles[p] += 1;
+            if (!c->batch_split)  // claimed launches: longest tiles first
+                std::stable_sort(tiles.begin(), tiles.end(), [](const BatchTile& x, const BatchTile& y) {
+                    return x.b - x.a > y.b - y.a;
+                });
+            cp.tiles.insert(cp.tiles.end(), tiles.begin(), tiles.end());
+            if (p == 0) cp.ntiles_first = (int)cp.tiles.size();
         }
     }
 }
@@ -585,7 +677,9 @@ const void* pass_rows_fn(const ClassPlan& cp) {
 int upload_class(snlm_ctx* c, LaunchSlot& s, const ClassPlan& cp, hipStream_t st) {
     const size_t off_jobs = align_up(sizeof(BatchHeader), 64);
     const size_t off_tiles = align_up(off_jobs + cp.jobs.size() * sizeof(BatchJob), 64);
-    const size_t tab_bytes = off_tiles + cp.tile_job.size() * sizeof(uint32_t);
+    const size_t off_first = align_up(off_tiles + cp.tiles.size() * sizeof(BatchTile), 64);
+    const size_t off_first2 = off_first + cp.first[0].size() * sizeof(uint32_t);
+    const size_t tab_bytes = off_first2 + cp.first[1].size() * sizeof(uint32_t);
     const size_t ncnt = 2 + cp.jobs.size();
     int rc = ensure_slot(c, s, tab_bytes, ncnt);
     if (rc) return rc;
@@ -593,11 +687,13 @@ int upload_class(snlm_ctx* c, LaunchSlot& s, const ClassPlan& cp, hipStream_t st
     BatchHeader hdr;
     hdr.njobs = (int)cp.jobs.size();
     hdr.ntiles_first = cp.ntiles_first;
-    hdr.ntiles = (int)(cp.tile_job.size() / 2);
+    hdr.ntiles = (int)cp.tiles.size();
     hdr.spin_limit = kSpinLimit;
     std::memcpy(s.h_tab, &hdr, sizeof(hdr));
     std::memcpy(s.h_tab + off_jobs, cp.jobs.data(), cp.jobs.size() * sizeof(BatchJob));
-    std::memcpy(s.h_tab + off_tiles, cp.tile_job.data(), cp.tile_job.size() * sizeof(uint32_t));
+    std::memcpy(s.h_tab + off_tiles, cp.tiles.data(), cp.tiles.size() * sizeof(BatchTile));
+    std::memcpy(s.h_tab + off_first, cp.first[0].data(), cp.first[0].size() * sizeof(uint32_t));
+    std::memcpy(s.h_tab + off_first2, cp.first[1].data(), cp.first[1].size() * sizeof(uint32_t));
     HIP_CHECK(c, hipMemcpyAsync(s.d_tab, s.h_tab, tab_bytes, hipMemcpyHostToDevice, st));
     HIP_CHECK(c, hipEventRecord(s.staged, st));
     s.fn = cp.fn[0];
@@ -609,6 +705,10 @@ int upload_class(snlm_ctx* c, LaunchSlot& s, const ClassPlan& cp, hipStream_t st
     s.ntiles_first = hdr.ntiles_first;
     s.off_jobs = off_jobs;
     s.off_tiles = off_tiles;
+    s.off_first[0] = off_first;
+    s.off_first[1] = off_first2;
+    s.workers[0] = (int)cp.first[0].size() - 1;
+    s.workers[1] = (int)cp.first[1].size() - 1;
     return SNLM_OK;
 }
 
@@ -622,32 +722,24 @@ int launch_class(snlm_ctx* c, LaunchSlot& s, hipStream_t st, uint32_t* d_status,
     std::memset(&a, 0, sizeof(a));
     a.hdr = (const BatchHeader*)s.d_tab;
     a.jobs = (const BatchJob*)(s.d_tab + s.off_jobs);
-    a.tile_job = (const uint32_t*)(s.d_tab + s.off_tiles);
+    a.tiles = (const BatchTile*)(s.d_tab + s.off_tiles);
     a.counters = s.d_cnt;
     a.status = d_status;
     KernelArgs a2 = a;
     int grid1, grid2 = 0;
     const void* f1 = split ? s.fn : s.fn_rows;
     const void* f2 = s.fn2;
-    const int cap = occupancy_grid(c, f1);
-    const int cap2 = occupancy_grid(c, f2);
     if (!split) {
         a.claim = s.d_cnt;
         a.tile_lo = 0;
         a.tile_hi = s.ntiles;
         a.wait = 1;
-        grid1 = std::max(1, std::min(cap, s.ntiles));
+        grid1 = std::max(1, std::min(occupancy_grid(c, f1), s.ntiles));
     } else {
-        a.claim = s.d_cnt;
-        a.tile_lo = 0;
-        a.tile_hi = s.ntiles_first;
-        a.wait = 0;
-        a2.claim = s.d_cnt + 1 + s.njobs;
-        a2.tile_lo = s.ntiles_first;
-        a2.tile_hi = s.ntiles;
-        a2.wait = 0;
-        grid1 = std::max(1, std::min(cap, s.ntiles_first));
-        grid2 = std::max(1, std::min(cap2, s.ntiles - s.ntiles_first));
+        a.worker_first = (const uint32_t*)(s.d_tab + s.off_first[0]);
+        a2.worker_first = (const uint32_t*)(s.d_tab + s.off_first[1]);
+        grid1 = s.workers[0];
+        grid2 = s.workers[1];
     }
     auto enqueue = [&](int ncnt_clear) -> hipError_t {
         const int gclear = (ncnt_clear + 255) / 256;
@@ -1118,7 +1210,7 @@ int snlm_autotune(snlm_ctx* c, const snlm_job* probe, int* best) {
 int snlm_autotune_batch(snlm_ctx* c, const snlm_job* jobs, int n, int* best) {
     if (!c) return SNLM_EINVAL;
     if (!jobs || n < 1) return fail(c, SNLM_EINVAL, "need at least one job");
-    static const int cand[] = {32, 48, 64, 96, 128, 160, 192, 256};
+    static const int cand[] = {1, 2, 3, 4};  // waves per SIMD
     std::vector<snlm_job> js(jobs, jobs + n);
     hipEvent_t e0, e1;
     HIP_CHECK(c, hipSetDevice(c->device));
@@ -1127,7 +1219,17 @@ int snlm_autotune_batch(snlm_ctx* c, const snlm_job* jobs, int n, int* best) {
     float best_ms = 1e30f;
     int choice = 0;
     for (int L : cand) {
-        for (auto& j : js) j.seg_len = L;
+        if (L > 1) {
+            int occ = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel_fn(js[0], 1), snlm::kLanes, 0) !=
+                    hipSuccess || L * 4 > occ)
+                break;
+        }
+        {
+            std::lock_guard<std::mutex> g(c->tune_mu);
+            for (auto& j : js) c->batch_tuned[class_of(j)] = L;
+            ++c->tune_epoch;
+        }
         float total = 0.0f;
         for (int rep = 0; rep < 4; ++rep) {
             int rc = snlm_denoise_batch(c, js.data(), n);
@@ -1174,7 +1276,7 @@ int snlm_autotune_save(snlm_ctx* c, const char* path) {
     std::fprintf(f, "\n], \"batch\": [");
     first = true;
     for (auto& kv : c->batch_tuned) {
-        std::fprintf(f, "%s\n  {\"bS\": %d, \"K\": %d, \"variant\": %d, \"order\": %d, \"seg_len\": %d}",
+        std::fprintf(f, "%s\n  {\"bS\": %d, \"K\": %d, \"variant\": %d, \"order\": %d, \"waves_per_simd\": %d}",
                      first ? "" : ",", kv.first.S, kv.first.K, kv.first.var, kv.first.order, kv.second);
         first = false;
     }
@@ -1213,9 +1315,9 @@ int snlm_autotune_load(snlm_ctx* c, const char* path) {
         ClassKey k;
         int seg = 0;
         if (std::sscanf(text.c_str() + pos,
-                        "{\"bS\": %d, \"K\": %d, \"variant\": %d, \"order\": %d, \"seg_len\": %d}",
+                        "{\"bS\": %d, \"K\": %d, \"variant\": %d, \"order\": %d, \"waves_per_simd\": %d}",
                         &k.S, &k.K, &k.var, &k.order, &seg) == 5 &&
-            seg > 0 && seg % kChunk == 0) {
+            seg >= 1 && seg <= 16) {
             c->batch_tuned[k] = seg;
             ++c->tune_epoch;
             ++loaded;

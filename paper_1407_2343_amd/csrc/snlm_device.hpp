@@ -63,12 +63,20 @@ struct PassDesc {
     float taps[kMaxK + 1]; // Gaussian taps g(0..K) (g(0) = 1)
 };
 
-// A batch: jobs, each with two passes, and a flat list of tiles (job, tile of
-// that job's pass).  Tiles of every first pass come before tiles of any
-// second pass; within a pass the host orders them longest first.
+// A batch: jobs, each with two passes, and a flat list of tiles.  A tile is
+// the samples [a, b) of the 64 lines of one group of one pass of one job (a
+// a multiple of kChunk).  Tiles of every first pass come before tiles of any
+// second pass.
 struct BatchJob {
     PassDesc pass[2];
-    int32_t tiles[2];      // tiles per pass (ngroups * nseg)
+    int32_t tiles[2];      // number of tiles of each pass of this job
+};
+
+// Tile t belongs to the first pass when t < BatchHeader::ntiles_first.
+struct BatchTile {
+    uint32_t job;
+    int32_t group;
+    int32_t a, b;
 };
 
 struct BatchHeader {
@@ -78,18 +86,25 @@ struct BatchHeader {
     uint32_t spin_limit;   // bound on dependency polls before giving up
 };
 
-// Kernel arguments.  direct mode (table == nullptr): grid = ngroups * nseg
-// workgroups of one wave; tile = blockIdx.x.  Batch mode: persistent grid
-// claiming tiles from the table.
+// Kernel arguments.
+// * direct (hdr == nullptr): grid = ngroups * nseg workgroups of one wave;
+//   workgroup t filters segment t / ngroups of group t % ngroups.
+// * static batch (worker_first != nullptr): workgroup k filters the tiles
+//   worker_first[k] .. worker_first[k+1] - 1 in order (the host cuts the work
+//   of the launch into equal shares, one per workgroup).
+// * claimed batch: persistent workgroups claim tiles [tile_lo, tile_hi) with
+//   an atomic counter; with wait, second-pass tiles wait for their job's
+//   first-pass tiles (per-job counters).
 struct KernelArgs {
     PassDesc direct;
     const BatchHeader* hdr;
     const BatchJob* jobs;
-    const uint32_t* tile_job;  // tile t -> job tile_job[2 t], its tile tile_job[2 t + 1]
+    const BatchTile* tiles;
+    const uint32_t* worker_first;
     uint32_t* counters;        // [1 + j] finished first-pass tiles of job j
     uint32_t* claim;           // claim counter of this launch
     uint32_t* status;          // set non-zero when a dependency wait gives up
-    int32_t tile_lo, tile_hi;  // tiles [lo, hi) of the flat list handled by this launch
+    int32_t tile_lo, tile_hi;  // tiles [lo, hi) handled by this launch (claimed mode)
     int32_t wait;              // second-pass tiles wait for their job's first pass
 };
 
@@ -202,9 +217,14 @@ struct LineIO {
 
     // Second half: for a staged chunk, wait for the loads and read this lane's
     // own samples p .. p + kChunk - 1 out of the tile.
-    __device__ __forceinline__ void finish_chunk(int p, float* v) const {
+    // stores_after: vector stores issued since the chunk's loads (the loads
+    // complete in order before them, so they need not be waited for).
+    __device__ __forceinline__ void finish_chunk(int p, float* v, bool four_stores_after) const {
         if (!chunk_staged(p)) return;
-        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the LDS-bound loads have landed
+        if (four_stores_after)
+            __builtin_amdgcn_s_waitcnt(0x0F74);  // vmcnt(4): loads landed, the 4 stores may fly
+        else
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
         __syncthreads();
         const int line = min(line0 + lane, nlines - 1);
         if (f16) {
@@ -229,7 +249,8 @@ struct LineIO {
     // below end, and only for active lanes).
     // stage_out requires every line start and c0 to be 4-element aligned, so
     // the 16-byte stores below are aligned.
-    __device__ __forceinline__ void store_chunk(int c0, int end, bool active, const float* y) const {
+    // Returns true when the chunk went out as the 4 tile stores.
+    __device__ __forceinline__ bool store_chunk(int c0, int end, bool active, const float* y) const {
         if (stage_out && c0 + kChunk <= end) {
 #pragma unroll
             for (int i = 0; i < kChunk; ++i) tile_out[lane * kStage + i] = y[i];
@@ -247,13 +268,14 @@ struct LineIO {
                 }
             }
             __syncthreads();
-            return;
+            return (line0 + 63 < nlines);  // all 4 stores issued by every lane
         }
         if (active) {
 #pragma unroll
             for (int i = 0; i < kChunk; ++i)
                 if (c0 + i < end) store(c0 + i, y[i]);
         }
+        return false;
     }
 };
 
@@ -364,8 +386,9 @@ __device__ __forceinline__ void run_segment(const PassDesc& d, const LineIO& io,
     }
 
     // ---- main chunks ----
+    bool staged_store_last = false;  // the previous chunk ended with 4 tile stores
     for (c0 = seg_a;; c0 += C) {
-        io.finish_chunk(c0 + S + K, nx);
+        io.finish_chunk(c0 + S + K, nx, staged_store_last);
         // shift the window by one chunk
 #pragma unroll
         for (int j = 0; j < NX - C; ++j) xs[j] = xs[j + C];
@@ -424,7 +447,7 @@ __device__ __forceinline__ void run_segment(const PassDesc& d, const LineIO& io,
 #pragma unroll
         for (int i = 0; i < C; i += 4)
             asm volatile("" ::"v"(y[i]), "v"(y[i + 1]), "v"(y[i + 2]), "v"(y[i + 3]));
-        io.store_chunk(c0, seg_b, active, y);
+        staged_store_last = io.store_chunk(c0, seg_b, active, y);
         if (!has_next) break;
     }
 }
@@ -467,14 +490,10 @@ __device__ __forceinline__ LineIO make_io(const PassDesc& d, int line0, int lane
 }
 
 template <int S, int K, bool GAUSS, bool KAHAN, bool ROWS>
-__device__ __forceinline__ void run_tile(const PassDesc& d, int tile, float* tiles) {
-    const int group = tile % d.ngroups;
-    const int seg = tile / d.ngroups;
+__device__ __forceinline__ void run_tile(const PassDesc& d, int group, int a, int b, float* tiles) {
     const int lane = threadIdx.x & (kLanes - 1);
     const int line0 = group * kLanes;
     const bool active = line0 + lane < d.nlines;
-    const int a = seg * d.seg_len;
-    const int b = min(a + d.seg_len, d.n);
     const LineIO io = make_io<ROWS>(d, line0, lane, tiles);
     if constexpr (S == 0) {
         run_copy(io, active, a, b);
@@ -506,22 +525,40 @@ __global__ __launch_bounds__(kLanes) void snlm_kernel(KernelArgs args) {
     if (batch) hdr = load_uniform(args.hdr);
     __shared__ uint32_t claimed;
     __shared__ __attribute__((aligned(16))) float tiles[ROWS ? kTileIn + kTileOut : 1];
+    const bool stat = batch && args.worker_first != nullptr;
+    uint32_t t_next = 0, t_end = 0;
+    if (stat) {
+        t_next = __builtin_amdgcn_readfirstlane(args.worker_first[blockIdx.x]);
+        t_end = __builtin_amdgcn_readfirstlane(args.worker_first[blockIdx.x + 1]);
+    }
     for (int iter = 0;; ++iter) {
         PassDesc d;
-        int tile, job = 0, pass = 0;
+        int group, a, b, job = 0, pass = 0;
         if (!batch) {
             if (iter > 0) break;
             d = args.direct;
-            tile = blockIdx.x;
+            const int t = blockIdx.x;
+            group = t % d.ngroups;
+            a = (t / d.ngroups) * d.seg_len;
+            b = min(a + d.seg_len, d.n);
         } else {
-            if (threadIdx.x == 0) claimed = atomicAdd(args.claim, 1u);
-            __syncthreads();
-            const uint32_t t = __builtin_amdgcn_readfirstlane(claimed) + (uint32_t)args.tile_lo;
-            __syncthreads();
-            if (t >= (uint32_t)args.tile_hi) break;
+            uint32_t t;
+            if (stat) {
+                if (t_next >= t_end) break;
+                t = t_next++;
+            } else {
+                if (threadIdx.x == 0) claimed = atomicAdd(args.claim, 1u);
+                __syncthreads();
+                t = __builtin_amdgcn_readfirstlane(claimed) + (uint32_t)args.tile_lo;
+                __syncthreads();
+                if (t >= (uint32_t)args.tile_hi) break;
+            }
+            const BatchTile bt = load_uniform(&args.tiles[t]);
+            job = (int)bt.job;
             pass = t < (uint32_t)hdr.ntiles_first ? 0 : 1;
-            job = (int)__builtin_amdgcn_readfirstlane(args.tile_job[2 * t]);
-            tile = (int)__builtin_amdgcn_readfirstlane(args.tile_job[2 * t + 1]);
+            group = bt.group;
+            a = bt.a;
+            b = bt.b;
             if (pass == 1 && args.wait) {
                 // Wait until every first-pass tile of this job has been written:
                 // poll with relaxed device-scope loads (no cache invalidation per
@@ -545,7 +582,7 @@ __global__ __launch_bounds__(kLanes) void snlm_kernel(KernelArgs args) {
             }
             d = load_uniform(&args.jobs[job].pass[pass]);
         }
-        run_tile<S, K, GAUSS, KAHAN, ROWS>(d, tile, tiles);
+        run_tile<S, K, GAUSS, KAHAN, ROWS>(d, group, a, b, tiles);
         if (batch && pass == 0 && args.wait) {
             // publish this tile's intermediate rows (one release per tile)
             __syncthreads();

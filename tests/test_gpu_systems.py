@@ -227,14 +227,14 @@ def test_batch_autotune_and_tuning_file(tmp_path):
     ctx.denoise_jobs(jobs, sync=True)
     before = [o.clone() for o in outs]
     best = ctx.autotune_batch(jobs)
-    assert best % 16 == 0 and best > 0
+    assert 1 <= best <= 4
     ctx.denoise_jobs(jobs, sync=True)
     for a, b in zip(before, outs):
         assert torch.equal(a, b)
     path = str(tmp_path / "tune.json")
     ctx.save_tuning(path)
     text = open(path).read()
-    assert '"batch"' in text and str(best) in text
+    assert '"batch"' in text and f'"waves_per_simd": {best}' in text
     other = _ctx(64 << 20)
     other.load_tuning(path)
     other.close()
