@@ -33,17 +33,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 S, K = 10, 3
-# VALU issue peak of MI355X without packed FP32 (not used by this build):
-# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-instructions/s.
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# Algorithmic VALU lane-instructions per unordered pair (u, u+s) of one pass,
-# box kernel, on the scaled samples: one lifted difference, two fused
-# multiply-adds for the window recursion (entering and leaving term), two fused
-# multiply-adds and two adds for the two accumulations.  The exp runs on the
-# transcendental unit alongside (measured: a 1:7 mix of v_exp_f32 and FMA
-# issues at 67.5 lane-ops/CU/clock, above the 64 of VALU alone), so it is not
-# counted against the VALU issue peak; its rate is reported separately.
-PAIR_VALU = 7
+# FP32 vector peak of MI355X from its unit counts and clock: 256 CUs x 4 SIMDs
+# x 32 FP32 lanes per clock x 2.4 GHz = 78.6 T lane-instructions/s (157.3
+# TFLOP/s counting an FMA as two).  Measured on the device: plain FP32
+# instructions (FMA, add, sub, mul, with or without VOP3 modifiers) from two
+# waves of one SIMD issue one wave64 instruction per 2.2 clocks; one wave alone
+# issues one per 4.4 clocks.
+VALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
+# Algorithmic lane-instructions per unordered pair (u, u+s) of one pass, box
+# kernel, on the scaled samples: one lifted difference, two fused multiply-adds
+# for the window recursion (entering and leaving term), one exp2 for the
+# weight, and two fused multiply-adds and two adds for the two accumulations.
+# The exp issues from the same VALU (and, measured, stops two waves of one SIMD
+# from pairing their FP32 instructions), so it is counted like the others.
+PAIR_VALU = 8
 
 
 def log(*a):
@@ -87,17 +90,71 @@ def cpu_baseline(items, budget_s: float = 12.0):
                       "S=10 K=3 box row_col, %.1f s wall" % (n, px, dt)}
 
 
+def source_sha():
+    """SHA-256 over the kernel source and the host planner (both decide the
+    bytes a batched step moves)."""
+    h = hashlib.sha256()
+    for f in ("snlm_device.hpp", "snlm_api.cpp"):
+        h.update(open(os.path.join(ROOT, "paper_1407_2343_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def traffic_from_profiles():
     """HBM bytes per batched step from the committed counter summary, if it was
-    taken on the current kernel source (else None)."""
+    taken on the current sources (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic_batch.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = open(os.path.join(ROOT, "paper_1407_2343_amd", "csrc", "snlm_device.hpp"), "rb").read()
-    if rec.get("device_source_sha256") != hashlib.sha256(src).hexdigest():
+    if rec.get("source_sha256") != source_sha():
         return None
     return rec.get("hbm_bytes_per_step")
+
+
+def write_traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_mib, last=6):
+    """Writes profiles/traffic_batch.json from four rocprofv3 --pmc counter
+    CSVs: FETCH_SIZE and WRITE_SIZE of a --profile-batch run, and the same two
+    counters of a --calibrate-copy run of copy_mib MiB.  Each batched launch
+    averages its last `last` dispatches (the timed steps)."""
+    import csv
+    from collections import defaultdict
+
+    def per_kernel(path, counter):
+        vals = defaultdict(dict)
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            vals[r["Kernel_Name"]][int(r["Dispatch_Id"])] = \
+                vals[r["Kernel_Name"]].get(int(r["Dispatch_Id"]), 0.0) + float(r["Counter_Value"])
+        return vals
+
+    def copy_kib(path, counter):
+        v = per_kernel(path, counter)
+        name = [k for k in v if "copyBuffer" in k][0]
+        return max(v[name].values())
+
+    copy_bytes = copy_mib << 20
+    ff = copy_bytes / (copy_kib(copy_fetch_csv, "FETCH_SIZE") * 1024.0)
+    wf = copy_bytes / (copy_kib(copy_write_csv, "WRITE_SIZE") * 1024.0)
+    fv, wv = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    launches = {}
+    for name in sorted(k for k in fv if "snlm_kernel" in k):
+        f = [fv[name][d] for d in sorted(fv[name])[-last:]]
+        w = [wv[name][d] for d in sorted(wv[name])[-last:]]
+        fk, wk = sum(f) / len(f), sum(w) / len(w)
+        launches[name] = {"FETCH_SIZE_KiB": fk, "WRITE_SIZE_KiB": wk,
+                          "bytes": fk * 1024 * ff + wk * 1024 * wf}
+    from paper_1407_2343_amd.synth import batch_workload
+    px = sum(img.size for img, _ in batch_workload(64, 128, 1024, seed=2000))
+    total = sum(v["bytes"] for v in launches.values())
+    rec = {"what": "HBM bytes of one batched step (first-pass + second-pass persistent launches) "
+                   "of the 64-image ragged batch, S=10 K=3 box row_col",
+           "fetch_factor": ff, "write_factor": wf, "launches": launches,
+           "hbm_bytes_per_step": int(total), "algorithmic_bytes_per_step": int(px * 16),
+           "ratio_to_algorithmic": total / (px * 16), "source_sha256": source_sha()}
+    with open(os.path.join(ROOT, "profiles", "traffic_batch.json"), "w") as fo:
+        json.dump(rec, fo, indent=1)
+    print(json.dumps({k: rec[k] for k in ("hbm_bytes_per_step", "ratio_to_algorithmic")}))
 
 
 # ----------------------------------------------------------------- serving --
@@ -248,7 +305,13 @@ def main():
                     help="only the batched steps (for rocprofv3 kernel traces and counters)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only a device-to-device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--write-traffic", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
+                                                         "COPY_WRITE_CSV", "COPY_MIB"),
+                    help="write profiles/traffic_batch.json from rocprofv3 counter CSVs (no GPU)")
     a = ap.parse_args()
+    if a.write_traffic:
+        write_traffic(*a.write_traffic[:4], int(a.write_traffic[4]))
+        return
     if a.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(independent images would shard across GPUs with no exchange).", file=sys.stderr)

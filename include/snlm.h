@@ -130,8 +130,8 @@ int snlm_denoise(snlm_ctx *ctx, const void *img, float *out, int H, int W, int S
 int snlm_denoise_ex(snlm_ctx *ctx, const snlm_job *job);
 
 /* Many images in two persistent launches per (S, K, kernel, order) class,
- * captured once in a HIP graph (counter reset + first-pass launch +
- * second-pass launch) and replayed.  The line groups of every image of a pass
+ * captured once in a HIP graph (first-pass launch + second-pass launch)
+ * and replayed.  The line groups of every image of a pass
  * are cut at 16-sample boundaries into one equal share of work per persistent
  * workgroup (jobs with seg_len > 0, and box jobs with plain or Kahan sums,
  * keep their segments whole).  The arena must hold the sum of the jobs'
@@ -194,7 +194,7 @@ int snlm_plan_seg_len(snlm_ctx *ctx, const snlm_job *job, int pass);
 
 /* Kernel timing for measurement.  enable = 1 clears and starts recording HIP
  * events on the stream of each persistent batched launch (immediately around
- * the graph replay: counter reset + persistent kernel) and of each direct
+ * the graph replay of its persistent kernels) and of each direct
  * pass launch; enable = 0 stops, waits for the recorded events and returns the
  * summed device time of batched launches in *batch_ms (count in *batch_n) and
  * of direct pass launches in *direct_ms (count in *direct_n).  Pointers may be

@@ -714,8 +714,10 @@ int upload_class(snlm_ctx* c, LaunchSlot& s, const ClassPlan& cp, hipStream_t st
 
 // Enqueues the persistent launch(es) of the class last uploaded into the
 // slot, as a replay of a captured graph (graphed = true) or as plain launches.
-// fused: one launch over all tiles, second-pass tiles waiting on per-image
-// counters; split: a launch over the first-pass tiles, then one over the rest.
+// split: a launch over the first-pass tiles, then one over the second-pass
+// tiles, each workgroup walking its own share; fused: a counter reset, then
+// one launch claiming all tiles, second-pass tiles waiting on per-image
+// counters.
 int launch_class(snlm_ctx* c, LaunchSlot& s, hipStream_t st, uint32_t* d_status, bool graphed) {
     const bool split = c->batch_split;
     KernelArgs a;
@@ -742,11 +744,14 @@ int launch_class(snlm_ctx* c, LaunchSlot& s, hipStream_t st, uint32_t* d_status,
         grid2 = s.workers[1];
     }
     auto enqueue = [&](int ncnt_clear) -> hipError_t {
-        const int gclear = (ncnt_clear + 255) / 256;
-        void* cargs[] = {(void*)&a.counters, (void*)&ncnt_clear};
-        hipError_t e = hipLaunchKernel((const void*)&snlm::snlm_clear_counters, dim3(gclear),
-                                       dim3(256), cargs, 0, st);
-        if (e != hipSuccess) return e;
+        hipError_t e = hipSuccess;
+        if (!split) {  // claim and dependency counters (static split launches use none)
+            const int gclear = (ncnt_clear + 255) / 256;
+            void* cargs[] = {(void*)&a.counters, (void*)&ncnt_clear};
+            e = hipLaunchKernel((const void*)&snlm::snlm_clear_counters, dim3(gclear), dim3(256),
+                                cargs, 0, st);
+            if (e != hipSuccess) return e;
+        }
         void* k1[] = {&a};
         e = hipLaunchKernel(f1, dim3(grid1), dim3(snlm::kLanes), k1, 0, st);
         if (e != hipSuccess || !split) return e;
