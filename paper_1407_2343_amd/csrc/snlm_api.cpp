@@ -743,23 +743,23 @@ int launch_class(snlm_ctx* c, LaunchSlot& s, hipStream_t st, uint32_t* d_status,
         grid1 = s.workers[0];
         grid2 = s.workers[1];
     }
-    auto enqueue = [&](int ncnt_clear) -> hipError_t {
+    auto enqueue = [&](int ncnt_clear, hipStream_t q) -> hipError_t {
         hipError_t e = hipSuccess;
         if (!split) {  // claim and dependency counters (static split launches use none)
             const int gclear = (ncnt_clear + 255) / 256;
             void* cargs[] = {(void*)&a.counters, (void*)&ncnt_clear};
             e = hipLaunchKernel((const void*)&snlm::snlm_clear_counters, dim3(gclear), dim3(256),
-                                cargs, 0, st);
+                                cargs, 0, q);
             if (e != hipSuccess) return e;
         }
         void* k1[] = {&a};
-        e = hipLaunchKernel(f1, dim3(grid1), dim3(snlm::kLanes), k1, 0, st);
+        e = hipLaunchKernel(f1, dim3(grid1), dim3(snlm::kLanes), k1, 0, q);
         if (e != hipSuccess || !split) return e;
         void* k2[] = {&a2};
-        return hipLaunchKernel(f2, dim3(grid2), dim3(snlm::kLanes), k2, 0, st);
+        return hipLaunchKernel(f2, dim3(grid2), dim3(snlm::kLanes), k2, 0, q);
     };
     if (!graphed) {
-        hipError_t e = enqueue(2 + s.njobs);
+        hipError_t e = enqueue(2 + s.njobs, st);
         if (e != hipSuccess) return hip_fail(c, e, "batched launch");
         return SNLM_OK;
     }
@@ -778,10 +778,12 @@ int launch_class(snlm_ctx* c, LaunchSlot& s, hipStream_t st, uint32_t* d_status,
             HIP_CHECK(c, hipGraphDestroy(s.graph));
             s.graph = nullptr;
         }
-        HIP_CHECK(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        hipError_t e1 = enqueue(graph_ncnt);
+        // captured on the library's own stream (the caller's may be the
+        // legacy default stream, which cannot be captured); replayed on st
+        HIP_CHECK(c, hipStreamBeginCapture(c->work, hipStreamCaptureModeThreadLocal));
+        hipError_t e1 = enqueue(graph_ncnt, c->work);
         hipGraph_t g = nullptr;
-        hipError_t e3 = hipStreamEndCapture(st, &g);
+        hipError_t e3 = hipStreamEndCapture(c->work, &g);
         if (e1 != hipSuccess) return hip_fail(c, e1, "capture of the batched launch");
         if (e3 != hipSuccess) return hip_fail(c, e3, "hipStreamEndCapture");
         s.graph = g;
@@ -1100,14 +1102,13 @@ int snlm_denoise_batch(snlm_ctx* c, const snlm_job* jobs, int n) {
     mix(&c->arena, sizeof(c->arena));
     mix(&c->tune_epoch, sizeof(c->tune_epoch));
     if (c->last_batch_classes > 0 && hash == c->last_batch_hash) {
+        // replay straight on the caller's stream: nothing to upload, no fences
         HIP_CHECK(c, hipSetDevice(c->device));
-        int rc = fence_in(c, c->work);
-        if (rc) return rc;
         for (int k = 0; k < c->last_batch_classes; ++k) {
-            rc = launch_class(c, c->slots[k], c->work, c->d_status, true);
+            int rc = launch_class(c, c->slots[k], c->user, c->d_status, true);
             if (rc) return rc;
         }
-        return fence_out(c, c->work);
+        return SNLM_OK;
     }
     c->last_batch_classes = 0;
     size_t need = 0;
@@ -1127,16 +1128,24 @@ int snlm_denoise_batch(snlm_ctx* c, const snlm_job* jobs, int n) {
     std::vector<ClassPlan> plans;
     plan_classes(c, js, mids, plans);
     if (c->slots.size() < plans.size()) c->slots.resize(plans.size());
+    // Tables go up on the library's stream once the caller's earlier work
+    // (which may still read the previous tables) is done; the launches then
+    // run on the caller's stream after the upload.
     int rc = fence_in(c, c->work);
     if (rc) return rc;
     for (size_t k = 0; k < plans.size(); ++k) {
         rc = upload_class(c, c->slots[k], plans[k], c->work);
-        if (!rc) rc = launch_class(c, c->slots[k], c->work, c->d_status, true);
+        if (rc) return rc;
+    }
+    rc = fence_out(c, c->work);
+    if (rc) return rc;
+    for (size_t k = 0; k < plans.size(); ++k) {
+        rc = launch_class(c, c->slots[k], c->user, c->d_status, true);
         if (rc) return rc;
     }
     c->last_batch_hash = hash;
     c->last_batch_classes = (int)plans.size();
-    return fence_out(c, c->work);
+    return SNLM_OK;
 }
 
 int snlm_sync(snlm_ctx* c) {
