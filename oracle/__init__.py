@@ -16,6 +16,8 @@ What it computes (Ghosh & Chaudhury, "Fast Separable Non-Local Means"):
 * ``snlm``     -- the separable RC / CR pipelines of Sec. 3.
 * ``pixel``    -- one output pixel of ``snlm``, for sampled checks of large images.
 * ``patch_d2`` -- one patch distance (eq. distanceSquared).
+* ``nlm1d_div`` -- 1D NLM with its divergence (Sec. 3.1, Alg. 3, eq. div).
+* ``sure``     -- the SURE-optimal combination of the two orders (Alg. 4).
 
 Pins (tests that tie it to something other than itself) live in
 ``tests/test_oracle_pins.py``: hand-derived closed forms, the PatchLift
@@ -78,6 +80,10 @@ class Oracle:
         lib.snlm_oracle_pixel.restype = D
         lib.snlm_oracle_patch_d2.argtypes = [dp, L, L, L, I, I, D]
         lib.snlm_oracle_patch_d2.restype = D
+        lib.snlm_oracle_nlm1d_div.argtypes = [dp, L, L, I, I, D, I, D, dp, L, dp, L, dp, L]
+        lib.snlm_oracle_nlm1d_div.restype = I
+        lib.snlm_oracle_sure.argtypes = [dp, L, L, L, I, I, D, I, D, D, dp, dp, dp, dp, dp, dp, dp, I]
+        lib.snlm_oracle_sure.restype = I
         lib.snlm_oracle_max_threads.argtypes = []
         lib.snlm_oracle_max_threads.restype = I
         self._lib = lib
@@ -129,6 +135,48 @@ class Oracle:
         return float(self._lib.snlm_oracle_patch_d2(_ptr(xa), xa.size, int(i), int(j), K, k,
                                                     _beta(k, K, beta)))
 
+    def nlm1d_div(self, x, S: int, K: int, h: float, kernel="box", beta=None, din=None):
+        """1D NLM of a line and its divergence dy(i)/dx(i) times din(i) (Alg. 3,
+        eq. div), in float64.  Returns (y, dout)."""
+        k = _KERNELS[kernel]
+        xa = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+        y = np.empty_like(xa)
+        d = np.empty_like(xa)
+        if din is not None:
+            da = np.ascontiguousarray(np.asarray(din, dtype=np.float64))
+            dptr = _ptr(da)
+        else:
+            dptr = ctypes.POINTER(ctypes.c_double)()
+        rc = self._lib.snlm_oracle_nlm1d_div(_ptr(xa), xa.size, 1, S, K, float(h), k,
+                                             _beta(k, K, beta), dptr, 1, _ptr(y), 1, _ptr(d), 1)
+        if rc != 0:
+            raise ValueError("oracle rejected the arguments")
+        return y, d
+
+    def sure(self, f, S: int, K: int, h: float, sigma: float, kernel="box", beta=None,
+             threads: int = 0) -> dict:
+        """SNLM with the SURE-optimal combination of the RC and CR orders
+        (Alg. 4), in float64.  Returns a dict with f_rc, f_cr, d_rc, d_cr, out,
+        theta (2,) and stats (7,)."""
+        k = _KERNELS[kernel]
+        fa = np.ascontiguousarray(np.asarray(f, dtype=np.float64))
+        if fa.ndim != 2:
+            raise ValueError("expected a 2D image")
+        H, W = fa.shape
+        res = {n: np.empty_like(fa) for n in ("f_rc", "f_cr", "d_rc", "d_cr", "out")}
+        theta = np.empty(2)
+        stats = np.empty(7)
+        nt = threads if threads > 0 else self.max_threads()
+        rc = self._lib.snlm_oracle_sure(_ptr(fa), H, W, W, S, K, float(h), k, _beta(k, K, beta),
+                                        float(sigma), _ptr(res["f_rc"]), _ptr(res["f_cr"]),
+                                        _ptr(res["d_rc"]), _ptr(res["d_cr"]), _ptr(res["out"]),
+                                        _ptr(theta), _ptr(stats), nt)
+        if rc != 0:
+            raise ValueError("oracle rejected the arguments")
+        res["theta"] = theta
+        res["stats"] = stats
+        return res
+
     def max_threads(self) -> int:
         """Threads an OpenMP region of the oracle uses by default."""
         return int(self._lib.snlm_oracle_max_threads())
@@ -161,6 +209,14 @@ def pixel(*a, **k):
 
 def patch_d2(*a, **k):
     return load().patch_d2(*a, **k)
+
+
+def nlm1d_div(*a, **k):
+    return load().nlm1d_div(*a, **k)
+
+
+def sure(*a, **k):
+    return load().sure(*a, **k)
 
 
 def max_threads() -> int:

@@ -190,6 +190,156 @@ double snlm_oracle_pixel(const double *f, long H, long W, long ld, int S, int K,
     return NAN;
 }
 
+/* ------------------------------------------------------------------------
+ * SURE-optimal combination of the two orders (Sec. 3.1, Alg. 3 and Alg. 4).
+ *
+ *   1D NLM with its divergence (Alg. 3, eq. div, Appendix): along with y(i),
+ *     P1 = sum_j w x(j),  P2 = sum_j w x(j)^2,  Q = sum_j w          (|j-i| <= S)
+ *     T1 = sum w g(i-j),  T2 = sum w g(i-j) x(j),  T3 = sum w g(i-j) x(2i-j),
+ *     T4 = sum w g(i-j) x(2i-j) x(j)                                (|j-i| <= K)
+ *     y = P1/Q,  T = T1 y x(i) - T2 x(i) - T3 y + T4,
+ *     dout(i) = din(i) * (h^2 + 2T + 2(P2 - Q y^2)) / (Q h^2)
+ *   (the closing parenthesis the printed listing lacks is placed so that the
+ *   expression equals eq. div: 1/W + (2/(h^2 W))(P2 - W y^2) + (2/(h^2 W)) T).
+ *   For h = +inf, or h^2 = 0, the limit 1/Q is used.  The formula is the
+ *   paper's, i.e. it treats x(j), j != i, as independent of x(i) even where the
+ *   reflection at a line end maps j onto i.
+ *
+ *   Alg. 4: delta = 1; rows then columns carry (f_r, delta_r) -> (f_rc,
+ *   delta_rc); columns then rows carry (f_c, delta_c) -> (f_cr, delta_cr); the
+ *   chained deltas are the divergences of eqs. partialrc / partialcr.  Then
+ *     A = [sum f_rc^2, sum f_rc f_cr; sum f_rc f_cr, sum f_cr^2]      (eq. A)
+ *     b = [sum f f_rc - sigma^2 sum delta_rc, sum f f_cr - sigma^2 sum delta_cr]
+ *                                                                      (eq. bb)
+ *   theta solves A theta = b, and the output is theta1 f_rc + theta2 f_cr
+ *   (eq. snlm).  When A is singular (f_rc proportional to f_cr, e.g. h = inf)
+ *   the minimum-norm minimiser theta1 = theta2 = (b1 + b2) / (sum of A) is used.
+ * ------------------------------------------------------------------------ */
+static void nlm1d_div_at(const double *x, long n, long stride, long i, int S, int K,
+                         double h, int kernel, double beta, double *yi, double *divi) {
+    double P1 = 0.0, P2 = 0.0, Q = 0.0, T1 = 0.0, T2 = 0.0, T3 = 0.0, T4 = 0.0;
+    const double xi = x[refl(i, n) * stride];
+    for (long j = i - S; j <= i + S; ++j) {
+        double d2 = patch_d2(x, n, stride, i, j, K, kernel, beta);
+        double w = (d2 == 0.0) ? 1.0 : exp(-d2 / (h * h));
+        double xj = x[refl(j, n) * stride];
+        P1 += w * xj;
+        P2 += w * xj * xj;
+        Q += w;
+        long dij = i - j;
+        if (dij >= -K && dij <= K) {
+            double g = tap((int)dij, kernel, beta);
+            double xm = x[refl(2 * i - j, n) * stride];
+            T1 += w * g;
+            T2 += w * g * xj;
+            T3 += w * g * xm;
+            T4 += w * g * xm * xj;
+        }
+    }
+    double y = P1 / Q;
+    double T = T1 * y * xi - T2 * xi - T3 * y + T4;
+    double h2 = h * h;
+    *yi = y;
+    if (isinf(h) || h2 == 0.0)
+        *divi = 1.0 / Q;
+    else
+        *divi = (h2 + 2.0 * T + 2.0 * (P2 - Q * y * y)) / (Q * h2);
+}
+
+/* 1D NLM with divergence of a strided line: y and dout = din * dy(i)/dx(i). */
+int snlm_oracle_nlm1d_div(const double *x, long n, long stride, int S, int K, double h,
+                          int kernel, double beta, const double *din, long dstride, double *y,
+                          long ystride, double *dout, long ostride) {
+    if (!x || !y || !dout || bad_args(n, S, K, h, kernel, beta)) return -1;
+    for (long i = 0; i < n; ++i) {
+        double yi, di;
+        nlm1d_div_at(x, n, stride, i, S, K, h, kernel, beta, &yi, &di);
+        y[i * ystride] = yi;
+        dout[i * ostride] = (din ? din[i * dstride] : 1.0) * di;
+    }
+    return 0;
+}
+
+/* One pass of Alg. 4 over every row (rows=1) or column: (in, din) -> (out, dout),
+ * all H x W with pitch W except in (pitch ld). */
+static void div_lines(const double *in, long ld, const double *din, long H, long W, int rows,
+                      int S, int K, double h, int kernel, double beta, double *out,
+                      double *dout, int nthreads) {
+    long nlines = rows ? H : W;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1)
+#endif
+    for (long l = 0; l < nlines; ++l) {
+        if (rows)
+            snlm_oracle_nlm1d_div(in + l * ld, W, 1, S, K, h, kernel, beta, din ? din + l * W : 0,
+                                  1, out + l * W, 1, dout + l * W, 1);
+        else
+            snlm_oracle_nlm1d_div(in + l, H, ld, S, K, h, kernel, beta, din ? din + l : 0, W,
+                                  out + l, W, dout + l, W);
+    }
+    (void)nthreads;
+}
+
+/* SNLM with the SURE-optimal combination (Alg. 4).  Outputs (pitch W, any may
+ * not be NULL): f_rc, f_cr, their chained divergences d_rc, d_cr, the combined
+ * image out, theta[2], and stats[7] = {sum f_rc^2, sum f_rc f_cr, sum f_cr^2,
+ * sum f f_rc, sum f f_cr, sum d_rc, sum d_cr}. */
+int snlm_oracle_sure(const double *f, long H, long W, long ld, int S, int K, double h,
+                     int kernel, double beta, double sigma, double *f_rc, double *f_cr,
+                     double *d_rc, double *d_cr, double *out, double *theta, double *stats,
+                     int nthreads) {
+    if (!f || !f_rc || !f_cr || !d_rc || !d_cr || !out || !theta || !stats) return -1;
+    if (H < 1 || W < 1 || ld < W || !(sigma >= 0.0)) return -1;
+    if (bad_args(H, S, K, h, kernel, beta) || bad_args(W, S, K, h, kernel, beta)) return -1;
+    size_t npx = (size_t)H * (size_t)W;
+    double *mid = (double *)malloc(sizeof(double) * npx);
+    double *dmid = (double *)malloc(sizeof(double) * npx);
+    if (!mid || !dmid) {
+        free(mid);
+        free(dmid);
+        return -1;
+    }
+    div_lines(f, ld, 0, H, W, 1, S, K, h, kernel, beta, mid, dmid, nthreads);
+    div_lines(mid, W, dmid, H, W, 0, S, K, h, kernel, beta, f_rc, d_rc, nthreads);
+    div_lines(f, ld, 0, H, W, 0, S, K, h, kernel, beta, mid, dmid, nthreads);
+    div_lines(mid, W, dmid, H, W, 1, S, K, h, kernel, beta, f_cr, d_cr, nthreads);
+    free(mid);
+    free(dmid);
+    double a11 = 0, a12 = 0, a22 = 0, c1 = 0, c2 = 0, s1 = 0, s2 = 0;
+    for (long r = 0; r < H; ++r)
+        for (long c = 0; c < W; ++c) {
+            size_t i = (size_t)r * W + c;
+            double x = f[r * ld + c];
+            a11 += f_rc[i] * f_rc[i];
+            a12 += f_rc[i] * f_cr[i];
+            a22 += f_cr[i] * f_cr[i];
+            c1 += x * f_rc[i];
+            c2 += x * f_cr[i];
+            s1 += d_rc[i];
+            s2 += d_cr[i];
+        }
+    double sg2 = sigma * sigma;
+    double b1 = c1 - sg2 * s1, b2 = c2 - sg2 * s2;
+    double det = a11 * a22 - a12 * a12;
+    if (det > 1e-12 * a11 * a22) {
+        theta[0] = (a22 * b1 - a12 * b2) / det;
+        theta[1] = (a11 * b2 - a12 * b1) / det;
+    } else {
+        double t = (b1 + b2) / (a11 + 2.0 * a12 + a22);
+        theta[0] = t;
+        theta[1] = t;
+    }
+    for (size_t i = 0; i < npx; ++i) out[i] = theta[0] * f_rc[i] + theta[1] * f_cr[i];
+    stats[0] = a11;
+    stats[1] = a12;
+    stats[2] = a22;
+    stats[3] = c1;
+    stats[4] = c2;
+    stats[5] = s1;
+    stats[6] = s2;
+    return 0;
+}
+
 /* Number of threads an OpenMP region would use (1 without OpenMP). */
 int snlm_oracle_max_threads(void) {
 #ifdef _OPENMP

@@ -229,9 +229,126 @@ def check_pixel_matches_full(orc):
             assert orc.pixel(f, r, c, 5, 2, 40.0, "gauss", order) == full[r, c]
 
 
+# ---- SURE combination (Sec. 3.1, Alg. 3, Alg. 4) ----------------------------
+def _fd_derivative(orc, x, i, S, K, h, kernel, eps):
+    """Central difference of the 1D NLM output at i with respect to x(i)."""
+    xp, xm = x.copy(), x.copy()
+    xp[i] += eps
+    xm[i] -= eps
+    return (orc.nlm1d(xp, S, K, h, kernel)[i] - orc.nlm1d(xm, S, K, h, kernel)[i]) / (2 * eps)
+
+
+def check_div_finite_difference(orc):
+    """eq. div against the derivative taken numerically from eq. 1dNLM itself,
+    at samples whose whole reach lies inside the line (no reflection)."""
+    rng = np.random.default_rng(21)
+    x = rng.normal(size=70) * 20 + 100
+    for kernel, S, K, h in (("box", 5, 2, 30.0), ("gauss", 6, 3, 40.0), ("box", 3, 0, 12.0)):
+        _, d = orc.nlm1d_div(x, S, K, h, kernel)
+        for i in range(S + 2 * K, x.size - S - 2 * K, 7):
+            fd = _fd_derivative(orc, x, i, S, K, h, kernel, 1e-4)
+            assert abs(fd - d[i]) < 1e-7 * max(1.0, abs(d[i])), (kernel, i, fd, d[i])
+
+
+def check_div_limits(orc):
+    """h = inf: y is a (2S+1)-tap average, whose derivative at the centre is
+    1/(2S+1); a tiny h makes y the identity (derivative 1); the divergence is
+    carried linearly through din."""
+    rng = np.random.default_rng(22)
+    x = rng.normal(size=40) * 30
+    y, d = orc.nlm1d_div(x, 4, 2, math.inf, "box")
+    assert np.max(np.abs(d - 1.0 / 9.0)) < 1e-15
+    y, d = orc.nlm1d_div(x, 4, 2, 1e-3, "gauss")
+    assert np.max(np.abs(y - x)) < 1e-12 and np.max(np.abs(d - 1.0)) < 1e-12
+    din = rng.uniform(0.5, 2.0, size=x.size)
+    _, d1 = orc.nlm1d_div(x, 4, 2, 25.0, "box")
+    _, d2 = orc.nlm1d_div(x, 4, 2, 25.0, "box", din=din)
+    assert np.max(np.abs(d2 - din * d1)) < 1e-14
+
+
+def _sure_phi(f, r, sigma, th):
+    """SURE of the combination (eq. sure with eq. linear), from its definition."""
+    out = th[0] * r["f_rc"] + th[1] * r["f_cr"]
+    n = f.size
+    return (np.mean((out - f) ** 2) - sigma ** 2
+            + 2 * sigma ** 2 / n * (th[0] * r["d_rc"].sum() + th[1] * r["d_cr"].sum()))
+
+
+def check_sure_minimiser(orc):
+    """theta from A theta = b (eqs. A, bb) is where the SURE of eq. sure, written
+    out directly, is stationary, and it is a minimum."""
+    f = _img(23, 29, 37)
+    sigma = 20.0
+    for kernel in ("box", "gauss"):
+        r = orc.sure(f, 4, 2, 60.0, sigma, kernel)
+        th = r["theta"]
+        assert np.max(np.abs(r["out"] - (th[0] * r["f_rc"] + th[1] * r["f_cr"]))) < 1e-9
+        e = 1e-4
+        for k in range(2):
+            tp, tm = th.copy(), th.copy()
+            tp[k] += e
+            tm[k] -= e
+            g = (_sure_phi(f, r, sigma, tp) - _sure_phi(f, r, sigma, tm)) / (2 * e)
+            assert abs(g) < 1e-6 * np.mean(f ** 2), (kernel, k, g)
+        base = _sure_phi(f, r, sigma, th)
+        for other in ((1.0, 0.0), (0.0, 1.0), (0.5, 0.5)):
+            assert base <= _sure_phi(f, r, sigma, np.array(other)) + 1e-9
+
+
+def check_sure_chain_and_orders(orc):
+    """delta_rc is the product of the row-pass divergence of f and the
+    column-pass divergence of the row-filtered image (eqs. partialrc,
+    partialcr), and f_rc / f_cr are the two orders of Sec. 3."""
+    f = _img(24, 19, 26)
+    S, K, h = 3, 2, 45.0
+    r = orc.sure(f, S, K, h, 10.0, "box")
+    assert np.max(np.abs(r["f_rc"] - orc.snlm(f, S, K, h, "box", "row_col"))) < 1e-10
+    assert np.max(np.abs(r["f_cr"] - orc.snlm(f, S, K, h, "box", "col_row"))) < 1e-10
+    fr = np.empty_like(f)
+    dr = np.empty_like(f)
+    for i in range(f.shape[0]):
+        fr[i], dr[i] = orc.nlm1d_div(f[i], S, K, h, "box")
+    dc = np.empty_like(f)
+    for j in range(f.shape[1]):
+        _, dc[:, j] = orc.nlm1d_div(fr[:, j], S, K, h, "box")
+    assert np.max(np.abs(r["d_rc"] - dr * dc)) < 1e-12
+
+
+def check_sure_transpose(orc):
+    """Transposing the image swaps the two orders, their divergences and theta."""
+    f = _img(25, 21, 30)
+    a = orc.sure(f, 3, 2, 50.0, 15.0, "gauss")
+    b = orc.sure(f.T, 3, 2, 50.0, 15.0, "gauss")
+    assert np.max(np.abs(a["f_rc"] - b["f_cr"].T)) < 1e-10
+    assert np.max(np.abs(a["d_cr"] - b["d_rc"].T)) < 1e-12
+    assert np.max(np.abs(a["theta"] - b["theta"][::-1])) < 1e-8
+
+
+def check_sure_tracks_mse(orc):
+    """With a known clean image and seeded Gaussian noise (eq. noise), the SURE
+    combination is no worse than either order (within 1 %), and SURE stays
+    close to the true MSE on average (it is unbiased up to the chain-rule
+    approximation of eqs. partialrc / partialcr)."""
+    from paper_1407_2343_amd.synth import clean_image
+    rel = []
+    for seed in (1, 2, 3):
+        rng = np.random.default_rng(seed)
+        f0 = clean_image(96, 96, rng).astype(np.float64)
+        sigma = 20.0
+        f = f0 + sigma * rng.standard_normal(f0.shape)
+        r = orc.sure(f, 5, 2, 150.0, sigma, "box")
+        mse = np.mean((r["out"] - f0) ** 2)
+        best = min(np.mean((r["f_rc"] - f0) ** 2), np.mean((r["f_cr"] - f0) ** 2))
+        assert mse <= 1.01 * best, (seed, mse, best)
+        rel.append((_sure_phi(f, r, sigma, r["theta"]) - mse) / mse)
+    assert abs(np.mean(rel)) < 0.1, rel
+
+
 ALL_CHECKS = [
     check_worked_examples_1d, check_separable_2x2, check_alg1_distances,
     check_difference_lift, check_patchlift_nlm, check_constant, check_h_inf_box_average,
     check_h_zero_identity, check_s0_identity, check_flips, check_transpose, check_affine,
-    check_k0_pixel_filter, check_pixel_matches_full,
+    check_k0_pixel_filter, check_pixel_matches_full, check_div_finite_difference,
+    check_div_limits, check_sure_minimiser, check_sure_chain_and_orders, check_sure_transpose,
+    check_sure_tracks_mse,
 ]

@@ -28,6 +28,15 @@ MUTANTS = {
     "normaliser_off_by_one": ("return P / Q;", "return P / (Q + 1.0);"),
     "tap_difference_unsquared": ("d2 += tap(k, kernel, beta) * (a - b) * (a - b);",
                                  "d2 += tap(k, kernel, beta) * (a - b);"),
+    "div_T_sign": ("double T = T1 * y * xi - T2 * xi - T3 * y + T4;",
+                   "double T = T1 * y * xi - T2 * xi - T3 * y - T4;"),
+    "div_drops_T": ("(h2 + 2.0 * T + 2.0 * (P2 - Q * y * y))", "(h2 + 2.0 * (P2 - Q * y * y))"),
+    "div_mirror_index": ("refl(2 * i - j, n)", "refl(2 * j - i, n)"),
+    "div_P2_from_centre": ("P2 += w * xj * xj;", "P2 += w * xi * xi;"),
+    "div_not_chained": ("(din ? din[i * dstride] : 1.0) * di", "di"),
+    "sure_b_sign": ("double b1 = c1 - sg2 * s1", "double b1 = c1 + sg2 * s1"),
+    "sure_second_pass_reads_input": ("div_lines(mid, W, dmid, H, W, 0,", "div_lines(f, ld, dmid, H, W, 0,"),
+    "sure_offdiag": ("a12 += f_rc[i] * f_cr[i];", "a12 += f_rc[i] * f_rc[i];"),
 }
 
 
