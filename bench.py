@@ -13,10 +13,12 @@ images one by one, and one 512 x 512 image in the four kernel/order
 variants), the roofline of the batched kernels (device time from HIP events
 on the stream they run on), the serving workload (2000 requests, Poisson
 arrivals, p50/p99 latency and Mpixel/s, against FIFO plain launches), the
-precision variants on a 4096 x 4096 image, and the FP64 oracle timed on the
-host cores on a bounded sample of the batch (``cpu_baseline``).
+precision variants on a 4096 x 4096 image, the SURE-optimal combination of
+the two orders on a 2048 x 2048 image (``sure_combination``), and the FP64
+oracle timed on the host cores on a bounded sample of the batch
+(``cpu_baseline``).
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-serve] [--no-precision] [--no-cpu]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-serve] [--no-precision] [--no-sure] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -293,6 +295,53 @@ def precision(torch, snlm, n=4096, sigma=30.0, nsample=24):
             "sampled_pixels": len(pts), "variants": out}
 
 
+# ----------------------------------------------------------- SURE combination --
+def sure_combination(torch, snlm, n=2048, sigma=30.0, nsample=6):
+    """SNLM with the SURE-optimal combination of the two orders (Alg. 4) on an
+    n x n image with a known clean image (eq. noise), S=10, K=3, box, h = 10
+    sigma: Mpixel/s of the whole call (four divergence-carrying passes, the
+    FP64 image sums, the 2x2 solve and the combination), theta, the MSE of each
+    order and of the combination against the clean image, and the SURE
+    estimate; parity at sampled pixels of f_cr against the FP64 oracle."""
+    import oracle
+    from paper_1407_2343_amd.synth import clean_image
+    rng = np.random.default_rng(6001)
+    f0 = clean_image(n, n, rng)
+    f = (f0 + sigma * rng.standard_normal(f0.shape)).astype(np.float32)
+    x = torch.from_numpy(f).to("cuda:0")
+    ctx = snlm.Context(arena_bytes=snlm.sure_workspace_bytes(n, n) + (1 << 20))
+    out = torch.empty_like(x)
+    res = {}
+
+    def call():
+        res["r"] = ctx.denoise_sure(x, S, K, 10 * sigma, sigma, "box", out=out)
+
+    ms, _ = time_steps(torch, call, 5, 2)
+    _, theta, stats = res["r"]
+    planes = ctx.sure_planes(n, n)
+    f_cr = planes["f_cr"].cpu().numpy().astype(np.float64)
+    d_rc = planes["d_rc"].cpu().numpy().astype(np.float64)
+    d_cr = planes["d_cr"].cpu().numpy().astype(np.float64)
+    y = out.cpu().numpy().astype(np.float64)
+    f_rc = (y - theta[1] * f_cr) / theta[0] if theta[0] != 0 else None
+    f0d, fd = f0.astype(np.float64), f.astype(np.float64)
+    mse = float(np.mean((y - f0d) ** 2))
+    phi = float(np.mean((y - fd) ** 2) - sigma ** 2
+                + 2 * sigma ** 2 / fd.size * (theta[0] * d_rc.sum() + theta[1] * d_cr.sum()))
+    pts = [(0, 0), (n - 1, n - 1)] + [(int(rng.integers(0, n)), int(rng.integers(0, n)))
+                                      for _ in range(nsample - 2)]
+    err = max(abs(f_cr[r, c] - oracle.pixel(fd, r, c, S, K, 10 * sigma, "box", "col_row")) for r, c in pts)
+    rec = {"image": "%dx%d sigma=%g S=%d K=%d box h=10 sigma" % (n, n, sigma, S, K),
+           "mpx_per_s": round(n * n / ms / 1e3, 1), "ms": round(ms, 3),
+           "theta": [round(t, 6) for t in theta], "mse_combined": round(mse, 4),
+           "sure": round(phi, 4), "f_cr_max_abs_vs_oracle_sampled": err}
+    if f_rc is not None:
+        rec["mse_row_col"] = round(float(np.mean((f_rc - f0d) ** 2)), 4)
+    rec["mse_col_row"] = round(float(np.mean((f_cr - f0d) ** 2)), 4)
+    ctx.close()
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -301,6 +350,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-sure", action="store_true")
     ap.add_argument("--profile-batch", action="store_true",
                     help="only the batched steps (for rocprofv3 kernel traces and counters)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -423,6 +473,9 @@ def main():
     if not a.no_precision:
         log("precision")
         result["precision"] = precision(torch, snlm)
+    if not a.no_sure:
+        log("sure combination")
+        result["sure_combination"] = sure_combination(torch, snlm)
     if not a.no_cpu:
         log("cpu baseline")
         result["cpu_baseline"] = cpu_baseline(items)

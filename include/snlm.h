@@ -143,6 +143,32 @@ int snlm_denoise_ex(snlm_ctx *ctx, const snlm_job *job);
  * counter, second-pass tiles waiting for the first-pass tiles of their image. */
 int snlm_denoise_batch(snlm_ctx *ctx, const snlm_job *jobs, int n);
 
+/* SURE-optimal combination of the two orders (Sec. 3.1, Alg. 3 and Alg. 4):
+ * out = theta1 f_rc + theta2 f_cr, where f_rc / f_cr are the row_col / col_row
+ * separable NLM of img, and theta solves the 2x2 system of eqs. A and bb built
+ * from image sums and the chained 1D divergences (eq. div; eqs. partialrc and
+ * partialcr), with sigma the noise level of eq. noise.  job->order is ignored;
+ * box jobs must use SNLM_SUM_BLOCK.  When f_rc and f_cr are proportional
+ * (singular system, e.g. h = +inf) theta1 = theta2 = (b1 + b2) / sum(A).
+ * The arena must hold snlm_sure_workspace_bytes(H, W); after the call it holds
+ * (snlm_sure_layout byte offsets): [0] scratch, [1] scratch, [2] f_cr, [3] the
+ * divergence of f_rc, [4] the divergence of f_cr (each H x Wp FP32, Wp = W
+ * rounded up to 16), [6] theta1, theta2 and the seven sums (doubles: sum f_rc^2,
+ * sum f_rc f_cr, sum f_cr^2, sum f f_rc, sum f f_cr, sum div_rc, sum div_cr).
+ * Enqueued on the context stream; when theta (2 doubles) or stats (7 doubles)
+ * are non-NULL host pointers the call waits for the result and copies it out.
+ * Errors: as snlm_denoise_ex, plus SNLM_EINVAL for sigma < 0 or not finite,
+ * and SNLM_ENOMEM when the arena is too small. */
+int snlm_denoise_sure(snlm_ctx *ctx, const snlm_job *job, float sigma, double *theta, double *stats);
+
+/* Arena bytes snlm_denoise_sure needs (0 for H or W < 1). */
+size_t snlm_sure_workspace_bytes(int H, int W);
+
+/* Byte offsets of the snlm_denoise_sure workspace regions: offsets[0..4] the
+ * five H x Wp FP32 planes, [5] partial sums, [6] result doubles, [7] total.
+ * SNLM_EINVAL for H or W < 1 or offsets NULL. */
+int snlm_sure_layout(int H, int W, size_t *offsets);
+
 /* Waits for everything enqueued on the context stream by this library and
  * reports device-side failures of batched launches (SNLM_EDEVICE). */
 int snlm_sync(snlm_ctx *ctx);

@@ -90,6 +90,13 @@ def lib():
             ip = ctypes.POINTER(ctypes.c_int)
             L.snlm_timing.argtypes = [vp, i, dp, ip, dp, ip]
             L.snlm_timing.restype = ctypes.c_int
+            L.snlm_denoise_sure.argtypes = [vp, jp, ctypes.c_float, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_double)]
+            L.snlm_denoise_sure.restype = ctypes.c_int
+            L.snlm_sure_workspace_bytes.argtypes = [i, i]
+            L.snlm_sure_workspace_bytes.restype = sz
+            L.snlm_sure_layout.argtypes = [i, i, ctypes.POINTER(sz)]
+            L.snlm_sure_layout.restype = ctypes.c_int
             L.snlm_strerror.argtypes = [i]
             L.snlm_strerror.restype = ctypes.c_char_p
             L.snlm_last_error.argtypes = [vp]
@@ -114,6 +121,19 @@ def version() -> str:
 
 def workspace_bytes(H: int, W: int, dtype: str = "f32") -> int:
     return int(lib().snlm_workspace_bytes(H, W, DTYPES[dtype]))
+
+
+def sure_workspace_bytes(H: int, W: int) -> int:
+    return int(lib().snlm_sure_workspace_bytes(H, W))
+
+
+def sure_layout(H: int, W: int) -> list:
+    """Byte offsets of the SURE workspace regions (see snlm_sure_layout)."""
+    off = (ctypes.c_size_t * 8)()
+    rc = lib().snlm_sure_layout(H, W, off)
+    if rc != OK:
+        raise SnlmError(rc, "snlm_sure_layout")
+    return list(off)
 
 
 def make_job(img=0, out=0, H=1, W=1, S=0, K=0, h=1.0, kernel="box", order="row_col",
@@ -225,6 +245,34 @@ class Context:
         self.check(lib().snlm_denoise_ex(self._ptr, ctypes.byref(job)), "snlm_denoise_ex")
         if sync:
             self.sync()
+        return out
+
+    def denoise_sure(self, x, S: int, K: int, h: float, sigma: float, kernel="box", beta=None,
+                     seg_len: int = 0, out=None):
+        """SURE-optimal combination of the two orders (Alg. 4).  Returns
+        (out, theta, stats); waits for the result."""
+        torch = _torch()
+        H, W = x.shape
+        if out is None:
+            out = torch.empty((H, W), dtype=torch.float32, device=x.device)
+        self.ensure_arena(sure_workspace_bytes(H, W))
+        job = self.job_for(x, out, S, K, h, kernel, "row_col", "block", beta, seg_len)
+        theta = (ctypes.c_double * 2)()
+        stats = (ctypes.c_double * 7)()
+        self.check(lib().snlm_denoise_sure(self._ptr, ctypes.byref(job), float(sigma), theta, stats),
+                   "snlm_denoise_sure")
+        return out, list(theta), list(stats)
+
+    def sure_planes(self, H: int, W: int) -> dict:
+        """Views of the SURE workspace after a call: f_cr and the divergences
+        of f_rc and f_cr (H x W FP32)."""
+        torch = _torch()
+        off = sure_layout(H, W)
+        Wp = (W + 15) // 16 * 16
+        out = {}
+        for k, name in ((2, "f_cr"), (3, "d_rc"), (4, "d_cr")):
+            plane = self.arena[off[k]:off[k] + H * Wp * 4].view(torch.float32).view(H, Wp)
+            out[name] = plane[:, :W]
         return out
 
     def denoise_job(self, job: Job):

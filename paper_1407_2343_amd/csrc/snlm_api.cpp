@@ -36,6 +36,95 @@ __global__ void snlm_clear_counters(uint32_t* counters, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) counters[i] = 0u;
 }
+
+// ---- SURE combination (Sec. 3.1, eqs. A and bb, Alg. 4) ----
+constexpr int kStatBlocks = 512;   // fixed grid: the FP64 sums are reproducible
+constexpr int kStatThreads = 256;
+constexpr int kStats = 7;          // sum f_rc^2, f_rc f_cr, f_cr^2, f f_rc, f f_cr, d_rc, d_cr
+
+struct StatArgs {
+    const void* f;        // noisy input (FP32 or FP16), pitch ld_f
+    const float* frc;     // pitch ld_rc
+    const float* fcr;     // pitch ld_x (as the divergences)
+    const float* drc;
+    const float* dcr;
+    double* partials;     // [kStatBlocks][8]
+    int H, W, ld_f, ld_rc, ld_x, f16;
+};
+
+// Per-block FP64 partial sums over a grid-stride walk of the pixels.
+__global__ __launch_bounds__(kStatThreads) void snlm_sure_stats(StatArgs a) {
+    __shared__ double red[kStatThreads][kStats + 1];
+    double acc[kStats] = {0, 0, 0, 0, 0, 0, 0};
+    const long n = (long)a.H * a.W;
+    for (long i = (long)blockIdx.x * kStatThreads + threadIdx.x; i < n; i += (long)kStatBlocks * kStatThreads) {
+        const int r = (int)(i / a.W), c = (int)(i % a.W);
+        const double x = a.f16 ? (double)((const _Float16*)a.f)[(long)r * a.ld_f + c]
+                               : (double)((const float*)a.f)[(long)r * a.ld_f + c];
+        const double u = a.frc[(long)r * a.ld_rc + c];
+        const double v = a.fcr[(long)r * a.ld_x + c];
+        acc[0] += u * u;
+        acc[1] += u * v;
+        acc[2] += v * v;
+        acc[3] += x * u;
+        acc[4] += x * v;
+        acc[5] += a.drc[(long)r * a.ld_x + c];
+        acc[6] += a.dcr[(long)r * a.ld_x + c];
+    }
+    for (int k = 0; k < kStats; ++k) red[threadIdx.x][k] = acc[k];
+    __syncthreads();
+    for (int w = kStatThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int k = 0; k < kStats; ++k) red[threadIdx.x][k] += red[threadIdx.x + w][k];
+        __syncthreads();
+    }
+    if (threadIdx.x < kStats) a.partials[blockIdx.x * 8 + threadIdx.x] = red[0][threadIdx.x];
+}
+
+// Sums the partials in a fixed order and solves A theta = b (one block).
+// out[0..1] = theta, out[2..8] = the seven sums.
+__global__ __launch_bounds__(kStatThreads) void snlm_sure_solve(const double* partials, double sigma2,
+                                                                double* out) {
+    __shared__ double red[kStatThreads][kStats + 1];
+    double acc[kStats] = {0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < kStatBlocks; b += kStatThreads)
+        for (int k = 0; k < kStats; ++k) acc[k] += partials[b * 8 + k];
+    for (int k = 0; k < kStats; ++k) red[threadIdx.x][k] = acc[k];
+    __syncthreads();
+    for (int w = kStatThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int k = 0; k < kStats; ++k) red[threadIdx.x][k] += red[threadIdx.x + w][k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double a11 = red[0][0], a12 = red[0][1], a22 = red[0][2];
+        const double b1 = red[0][3] - sigma2 * red[0][5];
+        const double b2 = red[0][4] - sigma2 * red[0][6];
+        const double det = a11 * a22 - a12 * a12;
+        double t1, t2;
+        if (det > 1e-12 * a11 * a22) {
+            t1 = (a22 * b1 - a12 * b2) / det;
+            t2 = (a11 * b2 - a12 * b1) / det;
+        } else {  // f_rc and f_cr proportional: the minimum-norm minimiser
+            t1 = t2 = (b1 + b2) / (a11 + 2.0 * a12 + a22);
+        }
+        out[0] = t1;
+        out[1] = t2;
+        for (int k = 0; k < kStats; ++k) out[2 + k] = red[0][k];
+    }
+}
+
+// out = theta1 f_rc + theta2 f_cr, in place over f_rc (eq. snlm).
+__global__ __launch_bounds__(256) void snlm_sure_combine(float* frc, int ld_rc, const float* fcr, int ld_x,
+                                                         int H, int W, const double* theta) {
+    const long n = (long)H * W;
+    const double t1 = theta[0], t2 = theta[1];
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const int r = (int)(i / W), c = (int)(i % W);
+        float* p = frc + (long)r * ld_rc + c;
+        *p = (float)(t1 * (double)*p + t2 * (double)fcr[(long)r * ld_x + c]);
+    }
+}
 }  // namespace snlm
 
 namespace {
@@ -90,6 +179,12 @@ bool pass_rows(const snlm_job& j, int pass) { return (pass == 0) == (j.order == 
 const void* kernel_fn(const snlm_job& j, int pass) {
     init_registry();
     return g_reg.fn[j.S][j.K][variant_of(j)][pass_rows(j, pass) ? 1 : 0];
+}
+
+// Divergence-carrying kernel of a job (both passes use it; no LDS tiles).
+const void* div_fn(const snlm_job& j) {
+    init_registry();
+    return g_reg.div[j.S][j.K][j.kernel == SNLM_GAUSS ? 1 : 0];
 }
 
 // Batched launches group jobs whose passes use the same two kernels.
@@ -996,6 +1091,22 @@ size_t snlm_workspace_bytes(int H, int W, snlm_dtype dtype) {
 
 size_t snlm_serving_bytes(int H, int W, snlm_dtype dtype) { return snlm_workspace_bytes(H, W, dtype); }
 
+int snlm_sure_layout(int H, int W, size_t* offsets) {
+    if (H < 1 || W < 1 || !offsets) return SNLM_EINVAL;
+    const size_t mb = mid_bytes(H, W);
+    for (int k = 0; k < 5; ++k) offsets[k] = (size_t)k * mb;
+    offsets[5] = 5 * mb;                                            // partial sums
+    offsets[6] = offsets[5] + align_up(snlm::kStatBlocks * 8 * sizeof(double), kAlign);  // result
+    offsets[7] = offsets[6] + align_up(16 * sizeof(double), kAlign);                      // total
+    return SNLM_OK;
+}
+
+size_t snlm_sure_workspace_bytes(int H, int W) {
+    size_t off[8];
+    if (snlm_sure_layout(H, W, off) != SNLM_OK) return 0;
+    return off[7];
+}
+
 int snlm_create(snlm_ctx** out, int device, void* stream, void* arena, size_t arena_bytes) {
     if (!out) return SNLM_EINVAL;
     *out = nullptr;
@@ -1064,6 +1175,94 @@ int snlm_denoise_ex(snlm_ctx* c, const snlm_job* j) {
         return fail(c, SNLM_ENOMEM, "arena smaller than snlm_workspace_bytes(H, W)");
     HIP_CHECK(c, hipSetDevice(c->device));
     return enqueue_job(c, *j, c->arena, c->user);
+}
+
+int snlm_denoise_sure(snlm_ctx* c, const snlm_job* j, float sigma, double* theta, double* stats) {
+    if (!c) return SNLM_EINVAL;
+    const char* why = check_job(j);
+    if (why) return fail(c, SNLM_EINVAL, why);
+    if (j->kernel == SNLM_BOX && j->sum != SNLM_SUM_BLOCK)
+        return fail(c, SNLM_EINVAL, "the SURE combination uses block-restarted sums");
+    if (!(sigma >= 0.0f) || std::isinf(sigma)) return fail(c, SNLM_EINVAL, "sigma must be finite and >= 0");
+    size_t off[8];
+    snlm_sure_layout(j->H, j->W, off);
+    if (off[7] > c->arena_bytes)
+        return fail(c, SNLM_ENOMEM, "arena smaller than snlm_sure_workspace_bytes(H, W)");
+    const void* fn = div_fn(*j);
+    if (!fn) return fail(c, SNLM_EDEVICE, "kernel variant not compiled");
+    HIP_CHECK(c, hipSetDevice(c->device));
+    char* ws = c->arena;
+    float* mid = (float*)(ws + off[0]);
+    float* dmid = (float*)(ws + off[1]);
+    float* fcr = (float*)(ws + off[2]);
+    float* drc = (float*)(ws + off[3]);
+    float* dcr = (float*)(ws + off[4]);
+    double* partials = (double*)(ws + off[5]);
+    double* result = (double*)(ws + off[6]);
+    const int Wp = mid_pitch(j->W);
+    const uint32_t dbytes = (uint32_t)((size_t)j->H * Wp * 4);
+    hipStream_t st = c->user;
+    // Alg. 4: rows then columns into (out, d_rc), columns then rows into (f_cr, d_cr).
+    for (int order = 0; order < 2; ++order) {
+        snlm_job jj = *j;
+        jj.order = order == 0 ? SNLM_ROW_COL : SNLM_COL_ROW;
+        if (order == 1) {
+            jj.out = fcr;
+            jj.ld_out = Wp;
+        }
+        for (int pass = 0; pass < 2; ++pass) {
+            snlm::DivArgs a;
+            std::memset(&a, 0, sizeof(a));
+            fill_pass(a.pass, jj, pass, mid, chosen_seg_len(c, jj, pass));
+            const bool rows = pass_rows(jj, pass);
+            a.din = pass == 0 ? nullptr : dmid;
+            a.dout = pass == 0 ? dmid : (order == 0 ? drc : dcr);
+            a.din_bytes = a.dout_bytes = dbytes;
+            a.d_line = rows ? Wp : 1;
+            a.d_pos = rows ? 1 : Wp;
+            void* args[] = {&a};
+            const int grid = a.pass.ngroups * a.pass.nseg;
+            HIP_CHECK(c, hipLaunchKernel(fn, dim3(grid), dim3(snlm::kLanes), args, 0, st));
+        }
+    }
+    snlm::StatArgs sa;
+    sa.f = j->img;
+    sa.frc = j->out;
+    sa.fcr = fcr;
+    sa.drc = drc;
+    sa.dcr = dcr;
+    sa.partials = partials;
+    sa.H = j->H;
+    sa.W = j->W;
+    sa.ld_f = j->ld_in;
+    sa.ld_rc = j->ld_out;
+    sa.ld_x = Wp;
+    sa.f16 = j->dtype == SNLM_F16;
+    void* sargs[] = {&sa};
+    HIP_CHECK(c, hipLaunchKernel((const void*)&snlm::snlm_sure_stats, dim3(snlm::kStatBlocks),
+                                 dim3(snlm::kStatThreads), sargs, 0, st));
+    double sigma2 = (double)sigma * (double)sigma;
+    void* vargs[] = {(void*)&partials, (void*)&sigma2, (void*)&result};
+    HIP_CHECK(c, hipLaunchKernel((const void*)&snlm::snlm_sure_solve, dim3(1), dim3(snlm::kStatThreads),
+                                 vargs, 0, st));
+    float* frc = j->out;
+    int ld_rc = j->ld_out, ld_x = Wp, H = j->H, W = j->W;
+    void* cargs[] = {(void*)&frc, (void*)&ld_rc, (void*)&fcr, (void*)&ld_x, (void*)&H, (void*)&W, (void*)&result};
+    const long npx = (long)H * W;
+    const int cgrid = (int)std::min<long>((npx + 255) / 256, 8192);
+    HIP_CHECK(c, hipLaunchKernel((const void*)&snlm::snlm_sure_combine, dim3(cgrid), dim3(256), cargs, 0, st));
+    if (theta || stats) {
+        double host[9];
+        HIP_CHECK(c, hipMemcpyAsync(host, result, sizeof(host), hipMemcpyDeviceToHost, st));
+        HIP_CHECK(c, hipStreamSynchronize(st));
+        if (theta) {
+            theta[0] = host[0];
+            theta[1] = host[1];
+        }
+        if (stats)
+            for (int k = 0; k < 7; ++k) stats[k] = host[2 + k];
+    }
+    return SNLM_OK;
 }
 
 int snlm_denoise(snlm_ctx* c, const void* img, float* out, int H, int W, int S, int K, float h,

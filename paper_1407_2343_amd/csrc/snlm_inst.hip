@@ -15,7 +15,10 @@ void register_k(KernelRegistry* reg) {
         const void* f = (const void*)&snlm_kernel<0, 0, false, false, false>;
         for (int v = 0; v < kNumVariants; ++v)
             for (int r = 0; r < 2; ++r) reg->fn[0][K][v][r] = f;
+        reg->div[0][K][0] = reg->div[0][K][1] = (const void*)&snlm_div_kernel<0, 0, false>;
     } else {
+        reg->div[SNLM_S][K][0] = (const void*)&snlm_div_kernel<SNLM_S, K, false>;
+        reg->div[SNLM_S][K][1] = (const void*)&snlm_div_kernel<SNLM_S, K, true>;
         reg->fn[SNLM_S][K][kVarBox][0] = (const void*)&snlm_kernel<SNLM_S, K, false, false, false>;
         reg->fn[SNLM_S][K][kVarBox][1] = (const void*)&snlm_kernel<SNLM_S, K, false, false, true>;
         reg->fn[SNLM_S][K][kVarBoxKahan][0] = (const void*)&snlm_kernel<SNLM_S, K, false, true, false>;

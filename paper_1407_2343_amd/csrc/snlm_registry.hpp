@@ -3,6 +3,7 @@
 #pragma once
 
 #include "snlm_device.hpp"
+#include "snlm_sure.hpp"
 
 namespace snlm {
 
@@ -10,8 +11,10 @@ enum Variant { kVarBox = 0, kVarBoxKahan = 1, kVarGauss = 2, kNumVariants = 3 };
 
 // fn[S][K][variant][rows]: rows = 1 is the variant for passes whose lines are
 // contiguous in memory (LDS transpose tiles), rows = 0 for column passes.
+// div[S][K][gauss]: divergence-carrying passes (block-restarted box, or Gauss).
 struct KernelRegistry {
     const void* fn[kMaxS + 1][kMaxK + 1][kNumVariants][2];
+    const void* div[kMaxS + 1][kMaxK + 1][2];
 };
 
 }  // namespace snlm

@@ -1,0 +1,286 @@
+// Divergence-carrying line pass for the SURE-optimal combination of the two
+// separable orders (Sec. 3.1: Alg. 3, eq. div, eqs. partialrc / partialcr).
+//
+// Along with the 1D NLM output y(i) of a line, the pass computes
+//   dout(i) = din(i) * dy(i)/dx(i),
+//   dy(i)/dx(i) = 1/Q + (2 / (h^2 Q)) (T + sum_j w (x(j) - y(i))^2),
+//   T = sum_{|j-i|<=K} w g(i-j) (x(j) - y(i)) (x(2i-j) - x(i)),
+// which is eq. div regrouped: the printed form's sum of w x(j)^2 minus Q y^2 is
+// the weighted spread of x(j) around y(i), and its four T accumulators expand
+// the same product.  The kernel accumulates both around the centre sample
+// instead, so that FP32 does not cancel:
+//   M  = sum_j w (x(j) - x(i))^2
+//   U1 = sum_{|j-i|<=K} w g (x(j) - x(i)) (x(2i-j) - x(i))
+//   U2 = sum_{|j-i|<=K} w g (x(2i-j) - x(i))
+// and at the output, with dx = y(i) - x(i):
+//   sum_j w (x(j) - y)^2 = M - Q dx^2,      T = U1 - dx U2.
+// Every term is carried on the scaled samples xs = a x (a^2 = log2(e) / h^2),
+// so 2 / h^2 becomes 2 ln 2.  Each unordered pair (i, i+s) contributes to both
+// of its centres, as in the plain pass; the y(i) it produces is bitwise the
+// plain pass's.
+#pragma once
+
+#include "snlm_device.hpp"
+
+namespace snlm {
+
+constexpr float kTwoLn2 = 1.3862943611198906f;
+
+struct DivArgs {
+    PassDesc pass;        // samples in and out, as for a plain pass (no LDS tiles)
+    const float* din;     // divergence carried in; nullptr: 1
+    float* dout;          // divergence out
+    uint32_t din_bytes, dout_bytes;
+    int32_t d_line;       // element stride between lines of both divergence buffers
+    int32_t d_pos;        // element stride between samples
+};
+
+struct DivLineIO {
+    __amdgpu_buffer_rsrc_t rin, rout;
+    int32_t base_b, pos_b;
+    bool has_in;
+
+    __device__ __forceinline__ float load(int p) const {
+        if (!has_in) return 1.0f;
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rin, base_b + p * pos_b, 0, 0));
+    }
+    __device__ __forceinline__ void store(int p, float v) const {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rout, base_b + p * pos_b, 0, 0);
+    }
+};
+
+template <int S, int K, bool GAUSS>
+__device__ __forceinline__ void run_segment_div(const PassDesc& d, const LineIO& io, const DivLineIO& dio,
+                                                bool active, int seg_a, int seg_b) {
+    constexpr int C = kChunk;
+    constexpr int NX = C + S + 2 * K + 1;  // x window: positions c0-K-1 .. c0+C+S+K-1
+    constexpr int NP = C + S;              // centres c0 .. c0+C+S-1
+    constexpr int ND = C + 2 * K;          // lifted samples of one diagonal (Gaussian)
+    constexpr int R0 = (C - S) % C;        // restart offset within a chunk
+    constexpr int XO = K + 1;              // x index of centre c0
+    constexpr int KU = K < S ? K : S;      // offsets whose pairs enter T (|j - i| <= K)
+    constexpr int NU = C + KU;             // centres c0 .. c0+C+KU-1 for U1, U2
+    static_assert(S >= 1 && S <= kMaxS && K >= 0 && K <= kMaxK, "parameter range");
+
+    const float alpha = d.alpha;
+    const float inv_alpha = d.inv_alpha;
+    const bool restart = d.restart != 0;
+    float xs[NX], P[NP], Q[NP], M[NP], U1[NU], U2[NU], nx[C];
+    float R[S];
+    float Dv[GAUSS ? ND : 1];
+    float g[K + 1];
+#pragma unroll
+    for (int k = 0; k <= K; ++k) g[k] = d.taps[k];
+
+    int c0 = seg_a - C;
+    io.template load<NX>(c0 - K - 1, xs);
+#pragma unroll
+    for (int j = 0; j < NX; ++j) xs[j] = alpha * xs[j];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        P[i] = xs[i + XO];
+        Q[i] = 1.0f;
+        M[i] = 0.0f;
+    }
+#pragma unroll
+    for (int i = 0; i < NU; ++i) {
+        U1[i] = 0.0f;
+        U2[i] = 0.0f;
+    }
+    io.issue_chunk(seg_a + S + K, nx);
+
+    auto lift_diag = [&](int s, int m0) {
+#pragma unroll
+        for (int m = 0; m < ND; ++m) {
+            if (m < m0) continue;
+            float dd = xs[m + 1] - xs[m + 1 + s];
+            Dv[m] = dd * dd;
+        }
+    };
+    auto gauss_d2 = [&](int i) -> float {
+        float r = Dv[i + K];
+#pragma unroll
+        for (int k = 1; k <= K; ++k) r = __builtin_fmaf(g[k], Dv[i + K - k] + Dv[i + K + k], r);
+        return r;
+    };
+    auto box_init = [&](int i, int s) -> float {
+        float r = 0.0f;
+#pragma unroll
+        for (int k = -K; k <= K; ++k) {
+            float dd = xs[i + XO + k] - xs[i + XO + k + s];
+            r = (k == -K) ? dd * dd : __builtin_fmaf(dd, dd, r);
+        }
+        return r;
+    };
+    auto box_slide = [&](int i, int s, int si) {
+        float de = xs[i + 2 * K + 1] - xs[i + 2 * K + 1 + s];
+        float dl = xs[i] - xs[i + s];
+        R[si] = __builtin_fmaf(-dl, dl, __builtin_fmaf(de, de, R[si]));
+    };
+    // Pair (i, i+s) of weight w: its partner terms for centre i+s, and, when
+    // centre_i, its terms for centre i.
+    auto pair = [&](int i, int s, float w, bool centre_i) {
+        const float xi = xs[i + XO];
+        const float xj = xs[i + s + XO];
+        const float dc = xi - xj;  // x(i) - x(i+s)
+        const float wd2 = w * (dc * dc);
+        if (centre_i) {
+            P[i] = __builtin_fmaf(w, xj, P[i]);
+            Q[i] += w;
+            M[i] += wd2;
+        }
+        P[i + s] = __builtin_fmaf(w, xi, P[i + s]);
+        Q[i + s] += w;
+        M[i + s] += wd2;
+        if (s <= KU) {
+            const float wg = GAUSS ? w * g[s] : w;
+            if (centre_i) {
+                const float t1 = wg * (xs[i - s + XO] - xi);  // w g (x(i-s) - x(i))
+                U1[i] = __builtin_fmaf(t1, -dc, U1[i]);       // times x(i+s) - x(i)
+                U2[i] += t1;
+            }
+            const float t2 = wg * (xs[i + 2 * s + XO] - xj);  // w g (x(i+2s) - x(i+s))
+            U1[i + s] = __builtin_fmaf(t2, dc, U1[i + s]);    // times x(i) - x(i+s)
+            U2[i + s] += t2;
+        }
+    };
+
+    // ---- pre-chunk: pairs (u, u+s) with u in [seg_a - s, seg_a) ----
+#pragma unroll
+    for (int s = 1; s <= S; ++s) {
+        const int si = s - 1;
+        if constexpr (GAUSS) lift_diag(s, C - s);
+#pragma unroll
+        for (int i = R0; i < C; ++i) {
+            float r;
+            if constexpr (GAUSS) {
+                if (i < C - s) continue;
+                r = gauss_d2(i);
+            } else {
+                if (i == R0)
+                    R[si] = box_init(i, s);
+                else
+                    box_slide(i, s, si);
+                if (i < C - s) continue;
+                r = R[si];
+            }
+            pair(i, s, __builtin_amdgcn_exp2f(-__builtin_fabsf(r)), false);
+        }
+    }
+
+    // ---- main chunks ----
+    for (c0 = seg_a;; c0 += C) {
+#pragma unroll
+        for (int j = 0; j < NX - C; ++j) xs[j] = xs[j + C];
+#pragma unroll
+        for (int t = 0; t < C; ++t) xs[NX - C + t] = alpha * nx[t];
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            P[i] = P[i + C];
+            Q[i] = Q[i + C];
+            M[i] = M[i + C];
+        }
+#pragma unroll
+        for (int i = S; i < NP; ++i) {
+            P[i] = xs[i + XO];
+            Q[i] = 1.0f;
+            M[i] = 0.0f;
+        }
+#pragma unroll
+        for (int i = 0; i < KU; ++i) {
+            U1[i] = U1[i + C];
+            U2[i] = U2[i + C];
+        }
+#pragma unroll
+        for (int i = KU; i < NU; ++i) {
+            U1[i] = 0.0f;
+            U2[i] = 0.0f;
+        }
+        const bool has_next = c0 + C < seg_b;
+        if (has_next) io.issue_chunk(c0 + C + S + K, nx);
+        float dv[C];
+#pragma unroll
+        for (int i = 0; i < C; ++i) dv[i] = dio.load(min(c0 + i, d.n - 1));
+
+#pragma unroll
+        for (int s = 1; s <= S; ++s) {
+            const int si = s - 1;
+            if constexpr (GAUSS) lift_diag(s, 0);
+#pragma unroll
+            for (int i = 0; i < C; ++i) {
+                float r;
+                if constexpr (GAUSS) {
+                    r = gauss_d2(i);
+                } else {
+                    box_slide(i, s, si);
+                    if (i == R0) {
+                        const float fresh = box_init(i, s);
+                        R[si] = restart ? fresh : R[si];
+                    }
+                    r = R[si];
+                }
+                pair(i, s, __builtin_amdgcn_exp2f(-__builtin_fabsf(r)), true);
+            }
+        }
+
+        float y[C], dd[C];
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            const float rq = __builtin_amdgcn_rcpf(Q[i]);
+            const float ys = P[i] * rq;
+            y[i] = ys * inv_alpha;
+            const float dx = ys - xs[i + XO];
+            const float spread = __builtin_fmaf(-(Q[i] * dx), dx, M[i]);
+            const float t = __builtin_fmaf(-dx, U2[i], U1[i]);
+            dd[i] = dv[i] * (__builtin_fmaf(kTwoLn2, t + spread, 1.0f) * rq);
+        }
+        io.store_chunk(c0, seg_b, active, y);
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < C; ++i)
+                if (c0 + i < seg_b) dio.store(c0 + i, dd[i]);
+        }
+        if (!has_next) break;
+    }
+}
+
+// S = 0: y = x and dy/dx = 1.
+__device__ __forceinline__ void run_copy_div(const LineIO& io, const DivLineIO& dio, bool active, int seg_a,
+                                             int seg_b) {
+    for (int p = seg_a; p < seg_b; ++p) {
+        float v[1];
+        io.template load<1>(p, v);
+        const float dv = dio.load(p);
+        if (active) {
+            io.store(p, v[0]);
+            dio.store(p, dv);
+        }
+    }
+}
+
+// One workgroup (one wave) per (line group, segment), as the direct plain pass.
+template <int S, int K, bool GAUSS>
+__global__ __launch_bounds__(kLanes) void snlm_div_kernel(DivArgs a) {
+    const PassDesc& d = a.pass;
+    const int t = blockIdx.x;
+    const int group = t % d.ngroups;
+    const int seg_a = (t / d.ngroups) * d.seg_len;
+    const int seg_b = min(seg_a + d.seg_len, d.n);
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int line0 = group * kLanes;
+    const bool active = line0 + lane < d.nlines;
+    const LineIO io = make_io<false>(d, line0, lane, nullptr);
+    DivLineIO dio;
+    const int line = min(line0 + lane, d.nlines - 1);
+    dio.rin = make_rsrc(a.din, a.din ? a.din_bytes : 0u);
+    dio.rout = make_rsrc(a.dout, a.dout_bytes);
+    dio.base_b = line * a.d_line * 4;
+    dio.pos_b = a.d_pos * 4;
+    dio.has_in = a.din != nullptr;
+    if constexpr (S == 0)
+        run_copy_div(io, dio, active, seg_a, seg_b);
+    else
+        run_segment_div<S, K, GAUSS>(d, io, dio, active, seg_a, seg_b);
+}
+
+}  // namespace snlm
