@@ -18,6 +18,8 @@ What it computes (Ghosh & Chaudhury, "Fast Separable Non-Local Means"):
 * ``patch_d2`` -- one patch distance (eq. distanceSquared).
 * ``nlm1d_div`` -- 1D NLM with its divergence (Sec. 3.1, Alg. 3, eq. div).
 * ``sure``     -- the SURE-optimal combination of the two orders (Alg. 4).
+* ``bilateral``, ``bf_params``, ``full`` -- the bilateral post-processing of
+  eq. BF with its parameter rules, and the whole SNLM[f] (Sec. 3.2, 4.1).
 
 Pins (tests that tie it to something other than itself) live in
 ``tests/test_oracle_pins.py``: hand-derived closed forms, the PatchLift
@@ -84,6 +86,10 @@ class Oracle:
         lib.snlm_oracle_nlm1d_div.restype = I
         lib.snlm_oracle_sure.argtypes = [dp, L, L, L, I, I, D, I, D, D, dp, dp, dp, dp, dp, dp, dp, I]
         lib.snlm_oracle_sure.restype = I
+        lib.snlm_oracle_bilateral.argtypes = [dp, L, L, L, D, D, dp, I]
+        lib.snlm_oracle_bilateral.restype = I
+        lib.snlm_oracle_bf_params.argtypes = [D, dp, dp]
+        lib.snlm_oracle_bf_params.restype = None
         lib.snlm_oracle_max_threads.argtypes = []
         lib.snlm_oracle_max_threads.restype = I
         self._lib = lib
@@ -177,6 +183,33 @@ class Oracle:
         res["stats"] = stats
         return res
 
+    def bilateral(self, f, sigma_s: float, sigma_r: float, threads: int = 0) -> np.ndarray:
+        """Bilateral filter of eq. BF (Sec. 3.2), in float64."""
+        fa = np.ascontiguousarray(np.asarray(f, dtype=np.float64))
+        H, W = fa.shape
+        out = np.empty_like(fa)
+        nt = threads if threads > 0 else self.max_threads()
+        rc = self._lib.snlm_oracle_bilateral(_ptr(fa), H, W, W, float(sigma_s), float(sigma_r),
+                                             _ptr(out), nt)
+        if rc != 0:
+            raise ValueError("oracle rejected the arguments")
+        return out
+
+    def bf_params(self, sigma: float):
+        """(sigma_s, sigma_r) of the bilateral parameter rules (Sec. 4.1)."""
+        a, b = ctypes.c_double(), ctypes.c_double()
+        self._lib.snlm_oracle_bf_params(float(sigma), ctypes.byref(a), ctypes.byref(b))
+        return a.value, b.value
+
+    def full(self, f, S: int, K: int, h: float, sigma: float, kernel="box", beta=None) -> dict:
+        """SNLM[f]: the SURE combination followed by the bilateral filter with
+        the parameter rules (Sec. 3.2, Sec. 4.1)."""
+        r = self.sure(f, S, K, h, sigma, kernel, beta)
+        ss, sr = self.bf_params(sigma)
+        r["snlm"] = self.bilateral(r["out"], ss, sr)
+        r["sigma_s"], r["sigma_r"] = ss, sr
+        return r
+
     def max_threads(self) -> int:
         """Threads an OpenMP region of the oracle uses by default."""
         return int(self._lib.snlm_oracle_max_threads())
@@ -217,6 +250,18 @@ def nlm1d_div(*a, **k):
 
 def sure(*a, **k):
     return load().sure(*a, **k)
+
+
+def bilateral(*a, **k):
+    return load().bilateral(*a, **k)
+
+
+def bf_params(*a, **k):
+    return load().bf_params(*a, **k)
+
+
+def full(*a, **k):
+    return load().full(*a, **k)
 
 
 def max_threads() -> int:

@@ -340,6 +340,52 @@ int snlm_oracle_sure(const double *f, long H, long W, long ld, int S, int K, dou
     return 0;
 }
 
+/* ------------------------------------------------------------------------
+ * Bilateral post-processing (Sec. 3.2, eq. BF) and its parameter rules
+ * (Sec. 4.1):
+ *   out(i) = sum_j w(j) g(f(i-j) - f(i)) f(i-j) / sum_j w(j) g(f(i-j) - f(i))
+ *   w(j) = exp(-|j|^2 / (2 sigma_s^2)),  g(t) = exp(-t^2 / (2 sigma_r^2)),
+ *   j over the integer offsets of [-3 sigma_s, 3 sigma_s]^2, i.e. |j1|, |j2| <=
+ *   floor(3 sigma_s);  the image is extended by the same half-sample symmetric
+ *   reflection as the NLM passes (the paper does not say).  sigma_r = +inf
+ *   gives g = 1 (a normalised Gaussian blur).
+ *   sigma_s = 2.5e-6 s^3 - 3.4e-4 s^2 + 0.021 s + 0.46,
+ *   sigma_r = 2.8e-4 s^3 - 0.088 s^2 + 8 s - 24,   s the noise level.
+ * ------------------------------------------------------------------------ */
+void snlm_oracle_bf_params(double sigma, double *sigma_s, double *sigma_r) {
+    double s2 = sigma * sigma, s3 = s2 * sigma;
+    if (sigma_s) *sigma_s = 2.5e-6 * s3 - 3.4e-4 * s2 + 0.021 * sigma + 0.46;
+    if (sigma_r) *sigma_r = 2.8e-4 * s3 - 0.088 * s2 + 8.0 * sigma - 24.0;
+}
+
+int snlm_oracle_bilateral(const double *f, long H, long W, long ld, double sigma_s,
+                          double sigma_r, double *out, int nthreads) {
+    if (!f || !out || H < 1 || W < 1 || ld < W) return -1;
+    if (!(sigma_s > 0.0) || !(sigma_r > 0.0)) return -1;
+    long R = (long)floor(3.0 * sigma_s);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1)
+#endif
+    for (long r = 0; r < H; ++r) {
+        for (long c = 0; c < W; ++c) {
+            double v = f[r * ld + c];
+            double num = 0.0, den = 0.0;
+            for (long dy = -R; dy <= R; ++dy)
+                for (long dx = -R; dx <= R; ++dx) {
+                    double u = f[refl(r - dy, H) * ld + refl(c - dx, W)];
+                    double ws = exp(-(double)(dy * dy + dx * dx) / (2.0 * sigma_s * sigma_s));
+                    double g = isinf(sigma_r) ? 1.0
+                                              : exp(-(u - v) * (u - v) / (2.0 * sigma_r * sigma_r));
+                    num += ws * g * u;
+                    den += ws * g;
+                }
+            out[r * W + c] = num / den;
+        }
+    }
+    (void)nthreads;
+    return 0;
+}
+
 /* Number of threads an OpenMP region would use (1 without OpenMP). */
 int snlm_oracle_max_threads(void) {
 #ifdef _OPENMP

@@ -344,11 +344,48 @@ def check_sure_tracks_mse(orc):
     assert abs(np.mean(rel)) < 0.1, rel
 
 
+# ---- bilateral post-processing (Sec. 3.2 eq. BF, Sec. 4.1 rules) -----------
+def check_bf_rules(orc):
+    for b in _parse_blocks(os.path.join(GOLDEN, "bilateral_rules.txt")):
+        ss, sr = orc.bf_params(float(b["sigma"]))
+        if "sigma_s" in b:
+            want, tol = (float(v) for v in b["sigma_s"].split())
+            assert abs(ss - want) <= tol, (b["case"], ss)
+        want, tol = (float(v) for v in b["sigma_r"].split())
+        assert abs(sr - want) <= tol, (b["case"], sr)
+
+
+def check_bf_gaussian_limit(orc):
+    """sigma_r = inf: a normalised Gaussian blur over the truncated square,
+    which is scipy's gaussian_filter with the same radius in 'reflect' mode."""
+    from scipy.ndimage import gaussian_filter
+    f = _img(31, 20, 27)
+    for ss in (0.7, 1.0):  # radius floor(3 ss) = round(3 ss) for these
+        got = orc.bilateral(f, ss, math.inf)
+        want = gaussian_filter(f, ss, mode="reflect", truncate=3.0)
+        assert np.max(np.abs(got - want)) < 1e-10, ss
+
+
+def check_bf_limits_and_invariants(orc):
+    f = _img(32, 18, 23)
+    # a tiny range width keeps every pixel (distinct values)
+    assert np.max(np.abs(orc.bilateral(f, 1.0, 1e-6) - f)) < 1e-12
+    c = np.full((7, 9), 42.5)
+    assert np.array_equal(orc.bilateral(c, 0.9, 30.0), c)
+    base = orc.bilateral(f, 1.2, 40.0)
+    for ax in ((0,), (1,), (0, 1)):
+        assert np.max(np.abs(orc.bilateral(np.flip(f, ax), 1.2, 40.0) - np.flip(base, ax))) < 1e-10
+    # range kernel on differences: BF(a f + b; |a| sigma_r) = a BF(f; sigma_r) + b
+    assert np.max(np.abs(orc.bilateral(-2.0 * f + 5.0, 1.2, 80.0) - (-2.0 * base + 5.0))) < 1e-9
+    # sigma_s below 1/3: only the centre tap
+    assert np.array_equal(orc.bilateral(f, 0.3, 40.0), f)
+
+
 ALL_CHECKS = [
     check_worked_examples_1d, check_separable_2x2, check_alg1_distances,
     check_difference_lift, check_patchlift_nlm, check_constant, check_h_inf_box_average,
     check_h_zero_identity, check_s0_identity, check_flips, check_transpose, check_affine,
     check_k0_pixel_filter, check_pixel_matches_full, check_div_finite_difference,
     check_div_limits, check_sure_minimiser, check_sure_chain_and_orders, check_sure_transpose,
-    check_sure_tracks_mse,
+    check_sure_tracks_mse, check_bf_rules, check_bf_gaussian_limit, check_bf_limits_and_invariants,
 ]

@@ -37,6 +37,13 @@ MUTANTS = {
     "sure_b_sign": ("double b1 = c1 - sg2 * s1", "double b1 = c1 + sg2 * s1"),
     "sure_second_pass_reads_input": ("div_lines(mid, W, dmid, H, W, 0,", "div_lines(f, ld, dmid, H, W, 0,"),
     "sure_offdiag": ("a12 += f_rc[i] * f_cr[i];", "a12 += f_rc[i] * f_rc[i];"),
+    "bf_support_ceil": ("long R = (long)floor(3.0 * sigma_s);", "long R = (long)ceil(3.0 * sigma_s);"),
+    "bf_spatial_unsquared": ("exp(-(double)(dy * dy + dx * dx) / (2.0 * sigma_s * sigma_s))",
+                             "exp(-(double)(labs(dy) + labs(dx)) / (2.0 * sigma_s * sigma_s))"),
+    "bf_range_against_centre_missing": ("exp(-(u - v) * (u - v) / (2.0 * sigma_r * sigma_r))",
+                                        "exp(-u * u / (2.0 * sigma_r * sigma_r))"),
+    "bf_rule_coefficient": ("- 0.088 * s2", "- 0.088 * s3"),
+    "bf_value_from_centre": ("num += ws * g * u;", "num += ws * g * v;"),
 }
 
 
