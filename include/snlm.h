@@ -161,6 +161,36 @@ int snlm_denoise_batch(snlm_ctx *ctx, const snlm_job *jobs, int n);
  * and SNLM_ENOMEM when the arena is too small. */
 int snlm_denoise_sure(snlm_ctx *ctx, const snlm_job *job, float sigma, double *theta, double *stats);
 
+/* Bilateral post-processing of eq. BF (Sec. 3.2):
+ *   out(i) = sum_j w(j) g(in(i-j) - in(i)) in(i-j) / sum_j w(j) g(in(i-j) - in(i)),
+ *   w(j) = exp(-|j|^2 / (2 sigma_s^2)),  g(t) = exp(-t^2 / (2 sigma_r^2)),
+ * over the integer offsets j of [-3 sigma_s, 3 sigma_s]^2, the image extended
+ * by half-sample symmetric reflection.  in, out: device FP32 H x W with row
+ * pitches ld_in, ld_out (elements); out must not overlap in.  sigma_r = +inf
+ * gives a normalised Gaussian blur.  Enqueued on the context stream.
+ * Errors: SNLM_EINVAL for NULL pointers, H or W < 1, pitches < W, overlap,
+ * sigma_s not in (0, 3) (the support radius floor(3 sigma_s) is at most 8),
+ * sigma_r not > 0. */
+int snlm_bilateral(snlm_ctx *ctx, const float *in, int ld_in, float *out, int ld_out, int H, int W,
+                   float sigma_s, float sigma_r);
+
+/* The bilateral parameters the paper's rules give for noise level sigma
+ * (Sec. 4.1): sigma_s = 2.5e-6 s^3 - 3.4e-4 s^2 + 0.021 s + 0.46 and
+ * sigma_r = 2.8e-4 s^3 - 0.088 s^2 + 8 s - 24.  Either pointer may be NULL. */
+void snlm_bilateral_params(float sigma, float *sigma_s, float *sigma_r);
+
+/* SNLM[f] of Sec. 3.2: the SURE-optimal combination of the two orders
+ * (snlm_denoise_sure) followed by the bilateral filter with the parameters of
+ * snlm_bilateral_params(sigma), written to job->out.  The arena must hold
+ * snlm_full_workspace_bytes(H, W): the snlm_sure_layout regions, then the
+ * combined image (H x Wp FP32) at byte offset snlm_sure_workspace_bytes(H, W).
+ * theta / stats as for snlm_denoise_sure.  Errors: as snlm_denoise_sure, plus
+ * SNLM_EINVAL when the rules give parameters snlm_bilateral rejects. */
+int snlm_denoise_full(snlm_ctx *ctx, const snlm_job *job, float sigma, double *theta, double *stats);
+
+/* Arena bytes snlm_denoise_full needs (0 for H or W < 1). */
+size_t snlm_full_workspace_bytes(int H, int W);
+
 /* Arena bytes snlm_denoise_sure needs (0 for H or W < 1). */
 size_t snlm_sure_workspace_bytes(int H, int W);
 

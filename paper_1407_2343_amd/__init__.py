@@ -97,6 +97,16 @@ def lib():
             L.snlm_sure_workspace_bytes.restype = sz
             L.snlm_sure_layout.argtypes = [i, i, ctypes.POINTER(sz)]
             L.snlm_sure_layout.restype = ctypes.c_int
+            fp = ctypes.POINTER(ctypes.c_float)
+            L.snlm_bilateral.argtypes = [vp, vp, i, vp, i, i, i, ctypes.c_float, ctypes.c_float]
+            L.snlm_bilateral.restype = ctypes.c_int
+            L.snlm_bilateral_params.argtypes = [ctypes.c_float, fp, fp]
+            L.snlm_bilateral_params.restype = None
+            L.snlm_denoise_full.argtypes = [vp, jp, ctypes.c_float, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_double)]
+            L.snlm_denoise_full.restype = ctypes.c_int
+            L.snlm_full_workspace_bytes.argtypes = [i, i]
+            L.snlm_full_workspace_bytes.restype = sz
             L.snlm_strerror.argtypes = [i]
             L.snlm_strerror.restype = ctypes.c_char_p
             L.snlm_last_error.argtypes = [vp]
@@ -125,6 +135,17 @@ def workspace_bytes(H: int, W: int, dtype: str = "f32") -> int:
 
 def sure_workspace_bytes(H: int, W: int) -> int:
     return int(lib().snlm_sure_workspace_bytes(H, W))
+
+
+def full_workspace_bytes(H: int, W: int) -> int:
+    return int(lib().snlm_full_workspace_bytes(H, W))
+
+
+def bilateral_params(sigma: float):
+    """(sigma_s, sigma_r) of the paper's bilateral rules for noise level sigma."""
+    a, b = ctypes.c_float(), ctypes.c_float()
+    lib().snlm_bilateral_params(float(sigma), ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
 
 
 def sure_layout(H: int, W: int) -> list:
@@ -261,6 +282,35 @@ class Context:
         stats = (ctypes.c_double * 7)()
         self.check(lib().snlm_denoise_sure(self._ptr, ctypes.byref(job), float(sigma), theta, stats),
                    "snlm_denoise_sure")
+        return out, list(theta), list(stats)
+
+    def bilateral(self, x, sigma_s: float, sigma_r: float, out=None):
+        """Bilateral filter of eq. BF on an FP32 device image."""
+        torch = _torch()
+        H, W = x.shape
+        if x.dtype != torch.float32 or x.stride(1) != 1:
+            raise ValueError("expected an FP32 image with unit column stride")
+        if out is None:
+            out = torch.empty((H, W), dtype=torch.float32, device=x.device)
+        self.check(lib().snlm_bilateral(self._ptr, ctypes.c_void_p(x.data_ptr()), x.stride(0),
+                                        ctypes.c_void_p(out.data_ptr()), out.stride(0), H, W,
+                                        float(sigma_s), float(sigma_r)), "snlm_bilateral")
+        return out
+
+    def denoise_full(self, x, S: int, K: int, h: float, sigma: float, kernel="box", beta=None,
+                     seg_len: int = 0, out=None):
+        """SNLM[f]: the SURE combination followed by the bilateral filter with
+        the paper's parameter rules.  Returns (out, theta, stats)."""
+        torch = _torch()
+        H, W = x.shape
+        if out is None:
+            out = torch.empty((H, W), dtype=torch.float32, device=x.device)
+        self.ensure_arena(full_workspace_bytes(H, W))
+        job = self.job_for(x, out, S, K, h, kernel, "row_col", "block", beta, seg_len)
+        theta = (ctypes.c_double * 2)()
+        stats = (ctypes.c_double * 7)()
+        self.check(lib().snlm_denoise_full(self._ptr, ctypes.byref(job), float(sigma), theta, stats),
+                   "snlm_denoise_full")
         return out, list(theta), list(stats)
 
     def sure_planes(self, H: int, W: int) -> dict:

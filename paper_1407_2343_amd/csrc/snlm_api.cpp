@@ -114,6 +114,48 @@ __global__ __launch_bounds__(kStatThreads) void snlm_sure_solve(const double* pa
     }
 }
 
+// ---- bilateral post-processing (Sec. 3.2, eq. BF) ----
+// One 16 x 16 tile of outputs per 256-thread workgroup; the (16 + 2R)^2 input
+// tile (reflected at the image borders) is staged in LDS.  Each tap's weight
+// is exp2(-(|j|^2 cs + (f(i-j) - f(i))^2 cr)), cs = log2(e) / (2 sigma_s^2),
+// cr = log2(e) / (2 sigma_r^2): the spatial and range Gaussians in one exp.
+constexpr int kBfTile = 16;
+constexpr int kBfMaxR = 8;
+
+__device__ __forceinline__ int bf_refl(int p, int n) {
+    while ((unsigned)p >= (unsigned)n) p = p < 0 ? -1 - p : 2 * n - 1 - p;
+    return p;
+}
+
+template <int R>
+__global__ __launch_bounds__(kBfTile * kBfTile) void snlm_bilateral_kernel(const float* in, int ld_in, float* out,
+                                                                            int ld_out, int H, int W, float cs,
+                                                                            float cr) {
+    constexpr int T = kBfTile + 2 * R;
+    __shared__ float tile[T][T + 1];
+    const int r0 = blockIdx.y * kBfTile, c0 = blockIdx.x * kBfTile;
+    for (int e = threadIdx.x; e < T * T; e += kBfTile * kBfTile) {
+        const int ty = e / T, tx = e % T;
+        tile[ty][tx] = in[(long)bf_refl(r0 - R + ty, H) * ld_in + bf_refl(c0 - R + tx, W)];
+    }
+    __syncthreads();
+    const int ty = threadIdx.x / kBfTile, tx = threadIdx.x % kBfTile;
+    const int r = r0 + ty, c = c0 + tx;
+    const float v = tile[ty + R][tx + R];
+    float num = 0.0f, den = 0.0f;
+#pragma unroll
+    for (int dy = -R; dy <= R; ++dy)
+#pragma unroll
+        for (int dx = -R; dx <= R; ++dx) {
+            const float u = tile[ty + R - dy][tx + R - dx];  // f(i - j)
+            const float d = u - v;
+            const float w = __builtin_amdgcn_exp2f(-__builtin_fmaf(d * d, cr, (float)(dy * dy + dx * dx) * cs));
+            num = __builtin_fmaf(w, u, num);
+            den += w;
+        }
+    if (r < H && c < W) out[(long)r * ld_out + c] = num / den;
+}
+
 // out = theta1 f_rc + theta2 f_cr, in place over f_rc (eq. snlm).
 __global__ __launch_bounds__(256) void snlm_sure_combine(float* frc, int ld_rc, const float* fcr, int ld_x,
                                                          int H, int W, const double* theta) {
@@ -1177,17 +1219,40 @@ int snlm_denoise_ex(snlm_ctx* c, const snlm_job* j) {
     return enqueue_job(c, *j, c->arena, c->user);
 }
 
-int snlm_denoise_sure(snlm_ctx* c, const snlm_job* j, float sigma, double* theta, double* stats) {
-    if (!c) return SNLM_EINVAL;
-    const char* why = check_job(j);
-    if (why) return fail(c, SNLM_EINVAL, why);
-    if (j->kernel == SNLM_BOX && j->sum != SNLM_SUM_BLOCK)
-        return fail(c, SNLM_EINVAL, "the SURE combination uses block-restarted sums");
-    if (!(sigma >= 0.0f) || std::isinf(sigma)) return fail(c, SNLM_EINVAL, "sigma must be finite and >= 0");
+namespace {
+
+int bilateral_enqueue(snlm_ctx* c, const float* in, int ld_in, float* out, int ld_out, int H, int W,
+                      float sigma_s, float sigma_r, hipStream_t st) {
+    const int R = (int)std::floor(3.0 * (double)sigma_s);
+    const double cs = 1.4426950408889634 / (2.0 * (double)sigma_s * sigma_s);
+    const double cr = std::isinf(sigma_r) ? 0.0 : 1.4426950408889634 / (2.0 * (double)sigma_r * sigma_r);
+    float fcs = (float)cs, fcr = (float)cr;
+    void* args[] = {(void*)&in, (void*)&ld_in, (void*)&out, (void*)&ld_out, (void*)&H, (void*)&W,
+                    (void*)&fcs, (void*)&fcr};
+    static const void* const fns[snlm::kBfMaxR + 1] = {
+        (const void*)&snlm::snlm_bilateral_kernel<0>, (const void*)&snlm::snlm_bilateral_kernel<1>,
+        (const void*)&snlm::snlm_bilateral_kernel<2>, (const void*)&snlm::snlm_bilateral_kernel<3>,
+        (const void*)&snlm::snlm_bilateral_kernel<4>, (const void*)&snlm::snlm_bilateral_kernel<5>,
+        (const void*)&snlm::snlm_bilateral_kernel<6>, (const void*)&snlm::snlm_bilateral_kernel<7>,
+        (const void*)&snlm::snlm_bilateral_kernel<8>};
+    dim3 grid((W + snlm::kBfTile - 1) / snlm::kBfTile, (H + snlm::kBfTile - 1) / snlm::kBfTile);
+    HIP_CHECK(c, hipLaunchKernel(fns[R], grid, dim3(snlm::kBfTile * snlm::kBfTile), args, 0, st));
+    return SNLM_OK;
+}
+
+const char* check_bilateral(float sigma_s, float sigma_r) {
+    if (!(sigma_s > 0.0f) || std::isinf(sigma_s)) return "sigma_s must be finite and > 0";
+    if (3.0 * (double)sigma_s >= snlm::kBfMaxR + 1) return "sigma_s too large (3 sigma_s must be < 9)";
+    if (!(sigma_r > 0.0f)) return "sigma_r must be > 0 (NaN rejected)";
+    return nullptr;
+}
+
+// The SURE combination of job j, written to (dst, ld_dst) (job->out when
+// dst is NULL).  ws: arena base of the snlm_sure_layout regions.
+int sure_enqueue(snlm_ctx* c, const snlm_job* j, float sigma, float* dst, int ld_dst, double* theta,
+                 double* stats) {
     size_t off[8];
     snlm_sure_layout(j->H, j->W, off);
-    if (off[7] > c->arena_bytes)
-        return fail(c, SNLM_ENOMEM, "arena smaller than snlm_sure_workspace_bytes(H, W)");
     const void* fn = div_fn(*j);
     if (!fn) return fail(c, SNLM_EDEVICE, "kernel variant not compiled");
     HIP_CHECK(c, hipSetDevice(c->device));
@@ -1206,6 +1271,10 @@ int snlm_denoise_sure(snlm_ctx* c, const snlm_job* j, float sigma, double* theta
     for (int order = 0; order < 2; ++order) {
         snlm_job jj = *j;
         jj.order = order == 0 ? SNLM_ROW_COL : SNLM_COL_ROW;
+        if (order == 0 && dst) {
+            jj.out = dst;
+            jj.ld_out = ld_dst;
+        }
         if (order == 1) {
             jj.out = fcr;
             jj.ld_out = Wp;
@@ -1226,8 +1295,10 @@ int snlm_denoise_sure(snlm_ctx* c, const snlm_job* j, float sigma, double* theta
         }
     }
     snlm::StatArgs sa;
+    float* frc = dst ? dst : j->out;
+    const int ld_rc = dst ? ld_dst : j->ld_out;
     sa.f = j->img;
-    sa.frc = j->out;
+    sa.frc = frc;
     sa.fcr = fcr;
     sa.drc = drc;
     sa.dcr = dcr;
@@ -1235,7 +1306,7 @@ int snlm_denoise_sure(snlm_ctx* c, const snlm_job* j, float sigma, double* theta
     sa.H = j->H;
     sa.W = j->W;
     sa.ld_f = j->ld_in;
-    sa.ld_rc = j->ld_out;
+    sa.ld_rc = ld_rc;
     sa.ld_x = Wp;
     sa.f16 = j->dtype == SNLM_F16;
     void* sargs[] = {&sa};
@@ -1245,8 +1316,7 @@ int snlm_denoise_sure(snlm_ctx* c, const snlm_job* j, float sigma, double* theta
     void* vargs[] = {(void*)&partials, (void*)&sigma2, (void*)&result};
     HIP_CHECK(c, hipLaunchKernel((const void*)&snlm::snlm_sure_solve, dim3(1), dim3(snlm::kStatThreads),
                                  vargs, 0, st));
-    float* frc = j->out;
-    int ld_rc = j->ld_out, ld_x = Wp, H = j->H, W = j->W;
+    int ld_x = Wp, H = j->H, W = j->W;
     void* cargs[] = {(void*)&frc, (void*)&ld_rc, (void*)&fcr, (void*)&ld_x, (void*)&H, (void*)&W, (void*)&result};
     const long npx = (long)H * W;
     const int cgrid = (int)std::min<long>((npx + 255) / 256, 8192);
@@ -1255,6 +1325,85 @@ int snlm_denoise_sure(snlm_ctx* c, const snlm_job* j, float sigma, double* theta
         double host[9];
         HIP_CHECK(c, hipMemcpyAsync(host, result, sizeof(host), hipMemcpyDeviceToHost, st));
         HIP_CHECK(c, hipStreamSynchronize(st));
+        if (theta) {
+            theta[0] = host[0];
+            theta[1] = host[1];
+        }
+        if (stats)
+            for (int k = 0; k < 7; ++k) stats[k] = host[2 + k];
+    }
+    return SNLM_OK;
+}
+
+const char* check_sure(const snlm_job* j, float sigma) {
+    const char* why = check_job(j);
+    if (why) return why;
+    if (j->kernel == SNLM_BOX && j->sum != SNLM_SUM_BLOCK) return "the SURE combination uses block-restarted sums";
+    if (!(sigma >= 0.0f) || std::isinf(sigma)) return "sigma must be finite and >= 0";
+    return nullptr;
+}
+
+}  // namespace
+
+int snlm_denoise_sure(snlm_ctx* c, const snlm_job* j, float sigma, double* theta, double* stats) {
+    if (!c) return SNLM_EINVAL;
+    const char* why = check_sure(j, sigma);
+    if (why) return fail(c, SNLM_EINVAL, why);
+    if (snlm_sure_workspace_bytes(j->H, j->W) > c->arena_bytes)
+        return fail(c, SNLM_ENOMEM, "arena smaller than snlm_sure_workspace_bytes(H, W)");
+    HIP_CHECK(c, hipSetDevice(c->device));
+    return sure_enqueue(c, j, sigma, nullptr, 0, theta, stats);
+}
+
+void snlm_bilateral_params(float sigma, float* sigma_s, float* sigma_r) {
+    const double s = sigma, s2 = s * s, s3 = s2 * s;
+    if (sigma_s) *sigma_s = (float)(2.5e-6 * s3 - 3.4e-4 * s2 + 0.021 * s + 0.46);
+    if (sigma_r) *sigma_r = (float)(2.8e-4 * s3 - 0.088 * s2 + 8.0 * s - 24.0);
+}
+
+int snlm_bilateral(snlm_ctx* c, const float* in, int ld_in, float* out, int ld_out, int H, int W, float sigma_s,
+                   float sigma_r) {
+    if (!c) return SNLM_EINVAL;
+    if (!in || !out) return fail(c, SNLM_EINVAL, "in and out must be non-NULL device pointers");
+    if (H < 1 || W < 1 || ld_in < W || ld_out < W) return fail(c, SNLM_EINVAL, "bad shape or pitch");
+    const char* why = check_bilateral(sigma_s, sigma_r);
+    if (why) return fail(c, SNLM_EINVAL, why);
+    const char* ib = (const char*)in;
+    const char* ob = (const char*)out;
+    const size_t ibytes = ((size_t)(H - 1) * ld_in + W) * 4, obytes = ((size_t)(H - 1) * ld_out + W) * 4;
+    if (ob < ib + ibytes && ib < ob + obytes) return fail(c, SNLM_EINVAL, "out overlaps in");
+    HIP_CHECK(c, hipSetDevice(c->device));
+    return bilateral_enqueue(c, in, ld_in, out, ld_out, H, W, sigma_s, sigma_r, c->user);
+}
+
+size_t snlm_full_workspace_bytes(int H, int W) {
+    if (H < 1 || W < 1) return 0;
+    return snlm_sure_workspace_bytes(H, W) + mid_bytes(H, W);
+}
+
+int snlm_denoise_full(snlm_ctx* c, const snlm_job* j, float sigma, double* theta, double* stats) {
+    if (!c) return SNLM_EINVAL;
+    const char* why = check_sure(j, sigma);
+    if (why) return fail(c, SNLM_EINVAL, why);
+    float ss, sr;
+    snlm_bilateral_params(sigma, &ss, &sr);
+    why = check_bilateral(ss, sr);
+    if (why) return fail(c, SNLM_EINVAL, std::string("bilateral parameters for this sigma: ") + why);
+    if (snlm_full_workspace_bytes(j->H, j->W) > c->arena_bytes)
+        return fail(c, SNLM_ENOMEM, "arena smaller than snlm_full_workspace_bytes(H, W)");
+    HIP_CHECK(c, hipSetDevice(c->device));
+    float* comb = (float*)(c->arena + snlm_sure_workspace_bytes(j->H, j->W));
+    const int Wp = mid_pitch(j->W);
+    int rc = sure_enqueue(c, j, sigma, comb, Wp, nullptr, nullptr);
+    if (rc) return rc;
+    rc = bilateral_enqueue(c, comb, Wp, j->out, j->ld_out, j->H, j->W, ss, sr, c->user);
+    if (rc) return rc;
+    if (theta || stats) {
+        size_t off[8];
+        snlm_sure_layout(j->H, j->W, off);
+        double host[9];
+        HIP_CHECK(c, hipMemcpyAsync(host, c->arena + off[6], sizeof(host), hipMemcpyDeviceToHost, c->user));
+        HIP_CHECK(c, hipStreamSynchronize(c->user));
         if (theta) {
             theta[0] = host[0];
             theta[1] = host[1];
