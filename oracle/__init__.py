@@ -18,6 +18,7 @@ What it computes (Ghosh & Chaudhury, "Fast Separable Non-Local Means"):
 * ``patch_d2`` -- one patch distance (eq. distanceSquared).
 * ``nlm1d_div`` -- 1D NLM with its divergence (Sec. 3.1, Alg. 3, eq. div).
 * ``sure``     -- the SURE-optimal combination of the two orders (Alg. 4).
+* ``snlm3d``   -- the separable NLM of a volume along three axes in turn.
 * ``bilateral``, ``bf_params``, ``full`` -- the bilateral post-processing of
   eq. BF with its parameter rules, and the whole SNLM[f] (Sec. 3.2, 4.1).
 
@@ -90,6 +91,8 @@ class Oracle:
         lib.snlm_oracle_bilateral.restype = I
         lib.snlm_oracle_bf_params.argtypes = [D, dp, dp]
         lib.snlm_oracle_bf_params.restype = None
+        lib.snlm_oracle_snlm3d.argtypes = [dp, L, L, L, I, I, D, I, D, ctypes.POINTER(I), dp, I]
+        lib.snlm_oracle_snlm3d.restype = I
         lib.snlm_oracle_max_threads.argtypes = []
         lib.snlm_oracle_max_threads.restype = I
         self._lib = lib
@@ -183,6 +186,24 @@ class Oracle:
         res["stats"] = stats
         return res
 
+    def snlm3d(self, f, S: int, K: int, h: float, kernel="box", axes="xyz", beta=None,
+               threads: int = 0) -> np.ndarray:
+        """Separable NLM of a D x H x W volume along the given axes in order
+        (x is the last, contiguous axis), in float64."""
+        k = _KERNELS[kernel]
+        fa = np.ascontiguousarray(np.asarray(f, dtype=np.float64))
+        if fa.ndim != 3:
+            raise ValueError("expected a 3D volume")
+        D, H, W = fa.shape
+        out = np.empty_like(fa)
+        ax = (ctypes.c_int * 3)(*["xyz".index(a) for a in axes])
+        nt = threads if threads > 0 else self.max_threads()
+        rc = self._lib.snlm_oracle_snlm3d(_ptr(fa), D, H, W, S, K, float(h), k, _beta(k, K, beta), ax,
+                                          _ptr(out), nt)
+        if rc != 0:
+            raise ValueError("oracle rejected the arguments")
+        return out
+
     def bilateral(self, f, sigma_s: float, sigma_r: float, threads: int = 0) -> np.ndarray:
         """Bilateral filter of eq. BF (Sec. 3.2), in float64."""
         fa = np.ascontiguousarray(np.asarray(f, dtype=np.float64))
@@ -250,6 +271,10 @@ def nlm1d_div(*a, **k):
 
 def sure(*a, **k):
     return load().sure(*a, **k)
+
+
+def snlm3d(*a, **k):
+    return load().snlm3d(*a, **k)
 
 
 def bilateral(*a, **k):

@@ -341,6 +341,59 @@ int snlm_oracle_sure(const double *f, long H, long W, long ld, int S, int K, dou
 }
 
 /* ------------------------------------------------------------------------
+ * Separable NLM of a volume (the extension to volumes noted in the
+ * conclusion): the 1D NLM of eq. 1dNLM along each axis in turn, axes[k] in
+ * {0 = x (contiguous), 1 = y, 2 = z}, each pass on the previous output.
+ * f and out are D x H x W with element (z, y, x) at (z H + y) W + x.
+ * ------------------------------------------------------------------------ */
+int snlm_oracle_snlm3d(const double *f, long D, long H, long W, int S, int K, double h,
+                       int kernel, double beta, const int *axes, double *out, int nthreads) {
+    if (!f || !out || !axes || D < 1 || H < 1 || W < 1) return -1;
+    if (bad_args(W, S, K, h, kernel, beta)) return -1;
+    int seen[3] = {0, 0, 0};
+    for (int k = 0; k < 3; ++k) {
+        if (axes[k] < 0 || axes[k] > 2 || seen[axes[k]]) return -1;
+        seen[axes[k]] = 1;
+    }
+    size_t npx = (size_t)D * H * W;
+    double *a = (double *)malloc(sizeof(double) * npx);
+    double *b = (double *)malloc(sizeof(double) * npx);
+    if (!a || !b) {
+        free(a);
+        free(b);
+        return -1;
+    }
+    memcpy(a, f, sizeof(double) * npx);
+    for (int k = 0; k < 3; ++k) {
+        int ax = axes[k];
+        long n = ax == 0 ? W : (ax == 1 ? H : D);
+        long stride = ax == 0 ? 1 : (ax == 1 ? W : H * W);
+        long nlines = (long)(npx / (size_t)n);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads > 0 ? nthreads : 1)
+#endif
+        for (long l = 0; l < nlines; ++l) {
+            long base;
+            if (ax == 0)
+                base = l * W;                             /* line (z, y) */
+            else if (ax == 1)
+                base = (l / W) * H * W + (l % W);         /* line (z, x) */
+            else
+                base = l;                                 /* line (y, x) */
+            snlm_oracle_nlm1d(a + base, n, stride, S, K, h, kernel, beta, b + base, stride);
+        }
+        double *t = a;
+        a = b;
+        b = t;
+    }
+    memcpy(out, a, sizeof(double) * npx);
+    free(a);
+    free(b);
+    (void)nthreads;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
  * Bilateral post-processing (Sec. 3.2, eq. BF) and its parameter rules
  * (Sec. 4.1):
  *   out(i) = sum_j w(j) g(f(i-j) - f(i)) f(i-j) / sum_j w(j) g(f(i-j) - f(i))

@@ -344,6 +344,39 @@ def check_sure_tracks_mse(orc):
     assert abs(np.mean(rel)) < 0.1, rel
 
 
+# ---- volumes ----------------------------------------------------------------
+def _vol(seed, D=5, H=9, W=13):
+    rng = np.random.default_rng(seed)
+    return rng.normal(size=(D, H, W)) * 25 + 120
+
+
+def check_3d_box_average(orc):
+    """h = inf: a (2S+1)-tap moving average along each axis (scipy's 'reflect'
+    mode is the half-sample symmetric extension)."""
+    f = _vol(41)
+    want = f
+    for ax in (2, 0, 1):  # axes "xzy"
+        want = uniform_filter1d(want, 2 * 3 + 1, axis=ax, mode="reflect")
+    got = orc.snlm3d(f, 3, 2, math.inf, "box", "xzy")
+    assert np.max(np.abs(got - want)) < 1e-10
+
+
+def check_3d_transpose_and_slices(orc):
+    """Permuting the axes of the volume permutes the filtered volume when the
+    pass order follows them; one slice (D = 1) is the 2D row_col filter, the
+    z pass on a single sample being the identity."""
+    f = _vol(42)
+    a = orc.snlm3d(f, 3, 2, 40.0, "gauss", "xyz")
+    # volume (z, y, x) -> (x, y, z): its x axis is the original z
+    b = orc.snlm3d(np.ascontiguousarray(f.transpose(2, 1, 0)), 3, 2, 40.0, "gauss", "zyx")
+    assert np.max(np.abs(a - b.transpose(2, 1, 0))) < 1e-10
+    s = _vol(43, 1, 11, 14)
+    got = orc.snlm3d(s, 4, 2, 35.0, "box", "xyz")[0]
+    assert np.max(np.abs(got - orc.snlm(s[0], 4, 2, 35.0, "box", "row_col"))) < 1e-10
+    c = np.full((3, 4, 6), -3.5)
+    assert np.array_equal(orc.snlm3d(c, 2, 1, 10.0, "box", "zxy"), c)
+
+
 # ---- bilateral post-processing (Sec. 3.2 eq. BF, Sec. 4.1 rules) -----------
 def check_bf_rules(orc):
     for b in _parse_blocks(os.path.join(GOLDEN, "bilateral_rules.txt")):
@@ -388,4 +421,5 @@ ALL_CHECKS = [
     check_k0_pixel_filter, check_pixel_matches_full, check_div_finite_difference,
     check_div_limits, check_sure_minimiser, check_sure_chain_and_orders, check_sure_transpose,
     check_sure_tracks_mse, check_bf_rules, check_bf_gaussian_limit, check_bf_limits_and_invariants,
+    check_3d_box_average, check_3d_transpose_and_slices,
 ]

@@ -44,6 +44,10 @@ MUTANTS = {
                                         "exp(-u * u / (2.0 * sigma_r * sigma_r))"),
     "bf_rule_coefficient": ("- 0.088 * s2", "- 0.088 * s3"),
     "bf_value_from_centre": ("num += ws * g * u;", "num += ws * g * v;"),
+    "vol_z_stride": ("long stride = ax == 0 ? 1 : (ax == 1 ? W : H * W);",
+                     "long stride = ax == 0 ? 1 : (ax == 1 ? W : H);"),
+    "vol_y_line_base": ("base = (l / W) * H * W + (l % W);", "base = l;"),
+    "vol_passes_not_chained": ("        double *t = a;\n        a = b;\n        b = t;\n", ""),
 }
 
 
