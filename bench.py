@@ -338,6 +338,24 @@ def sure_combination(torch, snlm, n=2048, sigma=30.0, nsample=6):
     if f_rc is not None:
         rec["mse_row_col"] = round(float(np.mean((f_rc - f0d) ** 2)), 4)
     rec["mse_col_row"] = round(float(np.mean((f_cr - f0d) ** 2)), 4)
+    # SNLM[f]: the combination followed by the bilateral filter (Sec. 3.2)
+    ctx.ensure_arena(snlm.full_workspace_bytes(n, n) + (1 << 20))
+    full = torch.empty_like(x)
+
+    def call_full():
+        res["f"] = ctx.denoise_full(x, S, K, 10 * sigma, sigma, "box", out=full)
+
+    ms_full, _ = time_steps(torch, call_full, 5, 2)
+    ss, sr = snlm.bilateral_params(sigma)
+    bf_out = torch.empty_like(x)
+    ms_bf, _ = time_steps(torch, lambda: ctx.bilateral(out, ss, sr, out=bf_out), 10, 2)
+    yf = full.cpu().numpy().astype(np.float64)
+    mse_full = float(np.mean((yf - f0d) ** 2))
+    rec["full_snlm"] = {"mpx_per_s": round(n * n / ms_full / 1e3, 1), "ms": round(ms_full, 3),
+                        "bilateral_ms": round(ms_bf, 3), "sigma_s": round(ss, 4), "sigma_r": round(sr, 3),
+                        "mse": round(mse_full, 4),
+                        "psnr_db": round(10 * np.log10(255.0 ** 2 / mse_full), 3),
+                        "psnr_db_before_bilateral": round(10 * np.log10(255.0 ** 2 / mse), 3)}
     ctx.close()
     return rec
 

@@ -191,6 +191,23 @@ int snlm_denoise_full(snlm_ctx *ctx, const snlm_job *job, float sigma, double *t
 /* Arena bytes snlm_denoise_full needs (0 for H or W < 1). */
 size_t snlm_full_workspace_bytes(int H, int W);
 
+/* Separable NLM of a volume (the extension to volumes noted in the paper's
+ * conclusion): the 1D NLM (eq. 1dNLM, same S, K, h, patch kernel, reflection
+ * and block-restarted sums as the 2D passes) along axes[0], then axes[1], then
+ * axes[2] of the previous pass's output, with 0 = x (the contiguous axis),
+ * 1 = y, 2 = z.  img: D x H x W, element (z, y, x) at (z H + y) ld_in + x,
+ * FP32 or FP16 per dtype; out: FP32, element at (z H + y) ld_out + x.  The
+ * arena must hold snlm_workspace3d_bytes(D, H, W) (two FP32 intermediate
+ * volumes).  Enqueued on the context stream.  Errors: SNLM_EINVAL for NULL
+ * pointers, D, H or W < 1, pitches < W, axes not a permutation of 0, 1, 2, the
+ * parameter checks of snlm_denoise, out overlapping img, or a volume over
+ * 2 GiB; SNLM_ENOMEM for a small arena; SNLM_EDEVICE. */
+int snlm_denoise3d(snlm_ctx *ctx, const void *img, int ld_in, snlm_dtype dtype, float *out, int ld_out,
+                   int D, int H, int W, int S, int K, float h, int kernel, const int *axes);
+
+/* Arena bytes snlm_denoise3d needs (0 for D, H or W < 1). */
+size_t snlm_workspace3d_bytes(int D, int H, int W);
+
 /* Arena bytes snlm_denoise_sure needs (0 for H or W < 1). */
 size_t snlm_sure_workspace_bytes(int H, int W);
 

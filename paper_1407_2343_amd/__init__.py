@@ -107,6 +107,11 @@ def lib():
             L.snlm_denoise_full.restype = ctypes.c_int
             L.snlm_full_workspace_bytes.argtypes = [i, i]
             L.snlm_full_workspace_bytes.restype = sz
+            L.snlm_denoise3d.argtypes = [vp, vp, i, i, vp, i, i, i, i, i, i, ctypes.c_float, i,
+                                         ctypes.POINTER(ctypes.c_int)]
+            L.snlm_denoise3d.restype = ctypes.c_int
+            L.snlm_workspace3d_bytes.argtypes = [i, i, i]
+            L.snlm_workspace3d_bytes.restype = sz
             L.snlm_strerror.argtypes = [i]
             L.snlm_strerror.restype = ctypes.c_char_p
             L.snlm_last_error.argtypes = [vp]
@@ -135,6 +140,13 @@ def workspace_bytes(H: int, W: int, dtype: str = "f32") -> int:
 
 def sure_workspace_bytes(H: int, W: int) -> int:
     return int(lib().snlm_sure_workspace_bytes(H, W))
+
+
+def workspace3d_bytes(D: int, H: int, W: int) -> int:
+    return int(lib().snlm_workspace3d_bytes(D, H, W))
+
+
+AXES = {"x": 0, "y": 1, "z": 2}
 
 
 def full_workspace_bytes(H: int, W: int) -> int:
@@ -312,6 +324,23 @@ class Context:
         self.check(lib().snlm_denoise_full(self._ptr, ctypes.byref(job), float(sigma), theta, stats),
                    "snlm_denoise_full")
         return out, list(theta), list(stats)
+
+    def denoise3d(self, x, S: int, K: int, h: float, kernel="box", axes="xyz", out=None):
+        """Separable NLM of a D x H x W volume along the axes in the given order
+        (a string over x, y, z; x is the contiguous axis)."""
+        torch = _torch()
+        if x.dim() != 3 or x.stride(2) != 1 or x.stride(0) != x.shape[1] * x.stride(1):
+            raise ValueError("expected a D x H x W volume with contiguous slices")
+        dt = {torch.float32: "f32", torch.float16: "f16"}[x.dtype]
+        D, H, W = x.shape
+        if out is None:
+            out = torch.empty((D, H, W), dtype=torch.float32, device=x.device)
+        self.ensure_arena(workspace3d_bytes(D, H, W))
+        ax = (ctypes.c_int * 3)(*[AXES[a] for a in axes])
+        self.check(lib().snlm_denoise3d(self._ptr, ctypes.c_void_p(x.data_ptr()), x.stride(1), DTYPES[dt],
+                                        ctypes.c_void_p(out.data_ptr()), out.stride(1), D, H, W, S, K,
+                                        float(h), KERNELS[kernel], ax), "snlm_denoise3d")
+        return out
 
     def sure_planes(self, H: int, W: int) -> dict:
         """Views of the SURE workspace after a call: f_cr and the divergences

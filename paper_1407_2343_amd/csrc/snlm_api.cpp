@@ -296,6 +296,8 @@ int heuristic_seg_len(int groups, int n, int target_waves) {
     return (nchunks + want - 1) / want * kChunk;
 }
 
+void fill_filter(PassDesc& d, const snlm_job& j, int seg_len);
+
 void fill_pass(PassDesc& d, const snlm_job& j, int pass, void* mid, int seg_len) {
     std::memset(&d, 0, sizeof(d));
     const bool rows_first = j.order == SNLM_ROW_COL;
@@ -325,6 +327,12 @@ void fill_pass(PassDesc& d, const snlm_job& j, int pass, void* mid, int seg_len)
     }
     d.nlines = rows ? H : W;
     d.n = rows ? W : H;
+    fill_filter(d, j, seg_len);
+}
+
+// The filter part of a pass descriptor (sums, segments, scale, taps); the
+// addressing fields and nlines, n must already be set.
+void fill_filter(PassDesc& d, const snlm_job& j, int seg_len) {
     const bool whole_line = j.kernel == SNLM_BOX && j.sum != SNLM_SUM_BLOCK;
     d.restart = (j.kernel == SNLM_BOX && j.sum == SNLM_SUM_BLOCK) ? 1 : 0;
     const int full = (d.n + kChunk - 1) / kChunk * kChunk;
@@ -1374,6 +1382,131 @@ int snlm_bilateral(snlm_ctx* c, const float* in, int ld_in, float* out, int ld_o
     if (ob < ib + ibytes && ib < ob + obytes) return fail(c, SNLM_EINVAL, "out overlaps in");
     HIP_CHECK(c, hipSetDevice(c->device));
     return bilateral_enqueue(c, in, ld_in, out, ld_out, H, W, sigma_s, sigma_r, c->user);
+}
+
+// ---------------------------------------------------------------- volumes --
+namespace {
+
+// Volume of D x H x W samples; element (z, y, x) at z * plane + y * pitch + x.
+struct VolView {
+    const void* p;
+    int pitch, plane;
+    bool f16;
+    uint32_t bytes;
+};
+
+// Pass along one axis (0 = x, 1 = y, 2 = z) of a volume.
+void fill_pass3d(PassDesc& d, const VolView& in, const VolView& out, int D, int H, int W, int axis,
+                 const snlm_job& j, int seg_len) {
+    std::memset(&d, 0, sizeof(d));
+    d.in = in.p;
+    d.in_f16 = in.f16;
+    d.in_bytes = in.bytes;
+    d.out = (float*)out.p;
+    d.out_bytes = out.bytes;
+    if (axis == 0) {  // lines (z, y) -> z * plane + y * pitch = line * pitch for contiguous slices
+        d.nlines = D * H;
+        d.n = W;
+        d.in_line = in.pitch;
+        d.in_pos = 1;
+        d.out_line = out.pitch;
+        d.out_pos = 1;
+    } else if (axis == 1) {  // lines (z, x)
+        d.nlines = D * W;
+        d.n = H;
+        d.split = W;
+        d.in_outer = in.plane;
+        d.in_line = 1;
+        d.in_pos = in.pitch;
+        d.out_outer = out.plane;
+        d.out_line = 1;
+        d.out_pos = out.pitch;
+    } else {  // lines (y, x)
+        d.nlines = H * W;
+        d.n = D;
+        d.split = W;
+        d.in_outer = in.pitch;
+        d.in_line = 1;
+        d.in_pos = in.plane;
+        d.out_outer = out.pitch;
+        d.out_line = 1;
+        d.out_pos = out.plane;
+    }
+    fill_filter(d, j, seg_len);
+}
+
+size_t vol_plane_bytes(int D, int H, int W) { return align_up((size_t)D * H * mid_pitch(W) * 4, kAlign); }
+
+}  // namespace
+
+size_t snlm_workspace3d_bytes(int D, int H, int W) {
+    if (D < 1 || H < 1 || W < 1) return 0;
+    return 2 * vol_plane_bytes(D, H, W);
+}
+
+int snlm_denoise3d(snlm_ctx* c, const void* img, int ld_in, snlm_dtype dtype, float* out, int ld_out, int D, int H,
+                   int W, int S, int K, float h, int kernel, const int* axes) {
+    if (!c) return SNLM_EINVAL;
+    if (!img || !out || !axes) return fail(c, SNLM_EINVAL, "img, out and axes must be non-NULL");
+    if (D < 1 || H < 1 || W < 1 || ld_in < W || ld_out < W) return fail(c, SNLM_EINVAL, "bad shape or pitch");
+    if (dtype != SNLM_F32 && dtype != SNLM_F16) return fail(c, SNLM_EINVAL, "unknown dtype");
+    bool seen[3] = {false, false, false};
+    for (int k = 0; k < 3; ++k) {
+        if (axes[k] < 0 || axes[k] > 2 || seen[axes[k]])
+            return fail(c, SNLM_EINVAL, "axes must be a permutation of 0, 1, 2");
+        seen[axes[k]] = true;
+    }
+    snlm_job j;
+    std::memset(&j, 0, sizeof(j));
+    j.img = img;
+    j.out = out;
+    j.H = H;
+    j.W = W;
+    j.ld_in = ld_in;
+    j.ld_out = ld_out;
+    j.dtype = dtype;
+    j.S = S;
+    j.K = K;
+    j.h = h;
+    j.kernel = (snlm_kernel)kernel;
+    j.order = SNLM_ROW_COL;
+    j.sum = SNLM_SUM_BLOCK;
+    const char* why = check_job(&j);  // S, K, h, kernel, and overlap of the first plane
+    if (why) return fail(c, SNLM_EINVAL, why);
+    const size_t esz = dtype == SNLM_F16 ? 2 : 4;
+    const double in_b = ((double)D * H - 1) * ld_in * esz + (double)W * esz;
+    const double out_b = (((double)D * H - 1) * ld_out + W) * 4.0;
+    if (in_b >= 2147483647.0 || out_b >= 2147483647.0 || (double)vol_plane_bytes(D, H, W) >= 2147483647.0)
+        return fail(c, SNLM_EINVAL, "volume larger than 2 GiB");
+    const char* ib = (const char*)img;
+    const char* ob = (const char*)out;
+    if (ob < ib + (size_t)in_b && ib < ob + (size_t)out_b) return fail(c, SNLM_EINVAL, "out overlaps img");
+    if (snlm_workspace3d_bytes(D, H, W) > c->arena_bytes)
+        return fail(c, SNLM_ENOMEM, "arena smaller than snlm_workspace3d_bytes(D, H, W)");
+    HIP_CHECK(c, hipSetDevice(c->device));
+    init_registry();
+    const int Wp = mid_pitch(W);
+    const uint32_t tb = (uint32_t)((size_t)D * H * Wp * 4);
+    VolView src{img, ld_in, H * ld_in, dtype == SNLM_F16, (uint32_t)in_b};
+    VolView t0{c->arena, Wp, H * Wp, false, tb};
+    VolView t1{c->arena + vol_plane_bytes(D, H, W), Wp, H * Wp, false, tb};
+    VolView dst{out, ld_out, H * ld_out, false, (uint32_t)out_b};
+    const VolView* ins[3] = {&src, &t0, &t1};
+    const VolView* outs[3] = {&t0, &t1, &dst};
+    for (int k = 0; k < 3; ++k) {
+        const int axis = axes[k];
+        const int n = axis == 0 ? W : (axis == 1 ? H : D);
+        const int nlines = axis == 0 ? D * H : (axis == 1 ? D * W : H * W);
+        const int groups = (nlines + snlm::kLanes - 1) / snlm::kLanes;
+        PassDesc d;
+        fill_pass3d(d, *ins[k], *outs[k], D, H, W, axis, j,
+                    heuristic_seg_len(groups, n, 4 * std::max(c->num_cu, 1)));
+        const void* fn = g_reg.fn[S][K][variant_of(j)][axis == 0 ? 1 : 0];
+        if (!fn) return fail(c, SNLM_EDEVICE, "kernel variant not compiled");
+        int rc = launch_direct(c, fn, d, c->user);
+        if (rc) return rc;
+    }
+    return SNLM_OK;
 }
 
 size_t snlm_full_workspace_bytes(int H, int W) {

@@ -58,6 +58,10 @@ struct PassDesc {
     int32_t seg_len;       // samples per segment (multiple of kChunk)
     int32_t nseg;          // segments per line = ceil(n / seg_len)
     int32_t ngroups;       // groups of 64 lines = ceil(nlines / 64)
+    int32_t split;         // 0: line l starts at l * in_line; else at (l / split) * in_outer
+                           // + (l % split) * in_line (and likewise for the output)
+    int32_t in_outer;      // element stride between blocks of `split` lines (input)
+    int32_t out_outer;     // element stride between blocks of `split` lines (output)
     float alpha;           // lift scale a = sqrt(log2 e) / h  (2^-64 when h = inf)
     float inv_alpha;       // 1 / a
     float taps[kMaxK + 1]; // Gaussian taps g(0..K) (g(0) = 1)
@@ -471,10 +475,16 @@ __device__ __forceinline__ LineIO make_io(const PassDesc& d, int line0, int lane
     io.rin = make_rsrc(d.in, d.in_bytes);
     io.rout = make_rsrc(d.out, d.out_bytes);
     const int esz = d.in_f16 ? 2 : 4;
-    io.in_base_b = line * d.in_line * esz;
+    int lin = line * d.in_line, lout = line * d.out_line;
+    if (d.split) {  // lines in blocks (a volume's y or z lines)
+        const int hi = line / d.split, lo = line - hi * d.split;
+        lin = hi * d.in_outer + lo * d.in_line;
+        lout = hi * d.out_outer + lo * d.out_line;
+    }
+    io.in_base_b = lin * esz;
     io.in_pos_b = d.in_pos * esz;
     io.in_line = d.in_line;
-    io.out_base_b = line * d.out_line * 4;
+    io.out_base_b = lout * 4;
     io.out_pos_b = d.out_pos * 4;
     io.out_line = d.out_line;
     io.line0 = line0;
@@ -482,8 +492,9 @@ __device__ __forceinline__ LineIO make_io(const PassDesc& d, int line0, int lane
     io.lane = lane;
     io.n = d.n;
     io.f16 = d.in_f16 != 0;
-    io.stage_in = ROWS && d.in_pos == 1 && ((uintptr_t)d.in & 15) == 0;
-    io.stage_out = ROWS && d.out_pos == 1 && (d.out_line & 3) == 0 && ((uintptr_t)d.out & 15) == 0;
+    io.stage_in = ROWS && d.split == 0 && d.in_pos == 1 && ((uintptr_t)d.in & 15) == 0;
+    io.stage_out = ROWS && d.split == 0 && d.out_pos == 1 && (d.out_line & 3) == 0 &&
+                   ((uintptr_t)d.out & 15) == 0;
     io.tile_in = tiles;
     io.tile_out = tiles + kTileIn;
     return io;
