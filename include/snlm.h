@@ -63,6 +63,11 @@ typedef enum {
     SNLM_SUM_KAHAN = 1,  /* recursion over the whole line, Kahan-compensated */
     SNLM_SUM_PLAIN = 2   /* recursion over the whole line, plain FP32 */
 } snlm_sum;
+/* With KAHAN or PLAIN, snlm_denoise_ex still cuts lines into segments: a scan
+ * first replays each offset's whole-line recursion and records its state at
+ * every segment start (a library-owned device buffer), so the result is
+ * bitwise the same as one segment per line.  Batched and served jobs with
+ * these modes keep one segment per line. */
 
 /* Limits of the compiled kernels. */
 #define SNLM_MAX_S 16

@@ -296,9 +296,11 @@ int heuristic_seg_len(int groups, int n, int target_waves) {
     return (nchunks + want - 1) / want * kChunk;
 }
 
-void fill_filter(PassDesc& d, const snlm_job& j, int seg_len);
+void fill_filter(PassDesc& d, const snlm_job& j, int seg_len, bool carry_ok = false);
 
-void fill_pass(PassDesc& d, const snlm_job& j, int pass, void* mid, int seg_len) {
+// carry_ok: whole-line (plain / Kahan) sums may be cut into segments, the
+// caller running the segment-start scan (snlm_carry_kernel) first.
+void fill_pass(PassDesc& d, const snlm_job& j, int pass, void* mid, int seg_len, bool carry_ok = false) {
     std::memset(&d, 0, sizeof(d));
     const bool rows_first = j.order == SNLM_ROW_COL;
     const bool rows = (pass == 0) ? rows_first : !rows_first;
@@ -327,16 +329,16 @@ void fill_pass(PassDesc& d, const snlm_job& j, int pass, void* mid, int seg_len)
     }
     d.nlines = rows ? H : W;
     d.n = rows ? W : H;
-    fill_filter(d, j, seg_len);
+    fill_filter(d, j, seg_len, carry_ok);
 }
 
 // The filter part of a pass descriptor (sums, segments, scale, taps); the
 // addressing fields and nlines, n must already be set.
-void fill_filter(PassDesc& d, const snlm_job& j, int seg_len) {
+void fill_filter(PassDesc& d, const snlm_job& j, int seg_len, bool carry_ok) {
     const bool whole_line = j.kernel == SNLM_BOX && j.sum != SNLM_SUM_BLOCK;
     d.restart = (j.kernel == SNLM_BOX && j.sum == SNLM_SUM_BLOCK) ? 1 : 0;
     const int full = (d.n + kChunk - 1) / kChunk * kChunk;
-    if (whole_line)
+    if (whole_line && !carry_ok)
         seg_len = full;  // running sums over the whole line: one segment
     else
         seg_len = std::min(std::max(seg_len, kChunk), full);
@@ -464,6 +466,8 @@ struct snlm_ctx {
     std::string last_error;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     uint32_t* d_status = nullptr;  // device-side failure flags of batched launches
+    float* d_carry = nullptr;      // segment-start states of whole-line sums (direct launches)
+    size_t carry_cap = 0;
     std::vector<LaunchSlot> slots;
     std::map<TuneKey, int> tuned;
     std::mutex tune_mu;
@@ -574,12 +578,43 @@ int launch_direct(snlm_ctx* c, const void* fn, const PassDesc& d, hipStream_t st
     return SNLM_OK;
 }
 
+// Segment-start scan kernel for whole-line sums with patch half-width K.
+template <int K>
+const void* carry_fn_k(int k, bool kahan) {
+    if (k == K)
+        return kahan ? (const void*)&snlm::snlm_carry_kernel<K, true> : (const void*)&snlm::snlm_carry_kernel<K, false>;
+    if constexpr (K < snlm::kMaxK) return carry_fn_k<K + 1>(k, kahan);
+    return nullptr;
+}
+const void* carry_fn(int K, bool kahan) { return carry_fn_k<0>(K, kahan); }
+
 int enqueue_job(snlm_ctx* c, const snlm_job& j, void* mid, hipStream_t st) {
     for (int pass = 0; pass < 2; ++pass) {
         const void* fn = kernel_fn(j, pass);
         if (!fn) return fail(c, SNLM_EDEVICE, "kernel variant not compiled");
         PassDesc d;
-        fill_pass(d, j, pass, mid, chosen_seg_len(c, j, pass));
+        fill_pass(d, j, pass, mid, chosen_seg_len(c, j, pass), true);
+        if (j.kernel == SNLM_BOX && !d.restart && d.nseg > 1 && j.S > 0) {
+            // whole-line sums in segments: the segment-start states first
+            const bool kahan = j.sum == SNLM_SUM_KAHAN;
+            const size_t need = (size_t)(d.nseg - 1) * j.S * d.nlines * (kahan ? 2 : 1) * sizeof(float);
+            if (c->carry_cap < need) {
+                if (c->d_carry) HIP_CHECK(c, hipFree(c->d_carry));
+                c->d_carry = nullptr;
+                c->carry_cap = 0;
+                HIP_CHECK(c, hipMalloc(&c->d_carry, need));
+                c->carry_cap = need;
+            }
+            snlm::CarryArgs ca;
+            std::memset(&ca, 0, sizeof(ca));
+            ca.pass = d;
+            ca.carry = c->d_carry;
+            ca.S = j.S;
+            void* cargs[] = {&ca};
+            const void* cfn = carry_fn(j.K, kahan);
+            HIP_CHECK(c, hipLaunchKernel(cfn, dim3(d.ngroups * j.S), dim3(snlm::kLanes), cargs, 0, st));
+            d.carry = c->d_carry;
+        }
         int rc = launch_direct(c, fn, d, st);
         if (rc) return rc;
     }
@@ -1210,6 +1245,7 @@ int snlm_destroy(snlm_ctx* c) {
             (void)hipEventDestroy(ev.second);
         }
     if (c->d_status) (void)hipFree(c->d_status);
+    if (c->d_carry) (void)hipFree(c->d_carry);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     if (c->ev_out) (void)hipEventDestroy(c->ev_out);
     if (c->work) (void)hipStreamDestroy(c->work);
@@ -1646,7 +1682,7 @@ int snlm_sync(snlm_ctx* c) {
 int snlm_plan_seg_len(snlm_ctx* c, const snlm_job* j, int pass) {
     if (!c || check_job(j) || pass < 0 || pass > 1) return SNLM_EINVAL;
     PassDesc d;
-    fill_pass(d, *j, pass, nullptr, chosen_seg_len(c, *j, pass));
+    fill_pass(d, *j, pass, nullptr, chosen_seg_len(c, *j, pass), true);
     return d.seg_len;
 }
 

@@ -65,6 +65,12 @@ struct PassDesc {
     float alpha;           // lift scale a = sqrt(log2 e) / h  (2^-64 when h = inf)
     float inv_alpha;       // 1 / a
     float taps[kMaxK + 1]; // Gaussian taps g(0..K) (g(0) = 1)
+    int32_t pad0;
+    // Whole-line running sums (plain or Kahan) cut into segments: the state of
+    // each offset's recursion at the start of every segment after the first,
+    // carry[((seg - 1) * S + s - 1) * nlines + line] (Kahan: the compensations
+    // follow, (nseg - 1) * S * nlines further on).  nullptr otherwise.
+    const float* carry;
 };
 
 // A batch: jobs, each with two passes, and a flat list of tiles.  A tile is
@@ -375,8 +381,16 @@ __device__ __forceinline__ void run_segment(const PassDesc& d, const LineIO& io,
                 r = gauss_d2(i);
             } else {
                 if (i == R0) {
-                    R[si] = box_init(i, s);
-                    if constexpr (KAHAN) Rc[si] = 0.0f;
+                    if (d.carry != nullptr && seg_a > 0) {
+                        // the whole-line recursion's state here (snlm_carry_kernel)
+                        const int line = min(io.line0 + io.lane, io.nlines - 1);
+                        const long at = ((long)(seg_a / d.seg_len - 1) * S + si) * io.nlines + line;
+                        R[si] = d.carry[at];
+                        if constexpr (KAHAN) Rc[si] = d.carry[at + (long)(d.nseg - 1) * S * io.nlines];
+                    } else {
+                        R[si] = box_init(i, s);
+                        if constexpr (KAHAN) Rc[si] = 0.0f;
+                    }
                 } else {
                     box_slide(i, s, si);
                 }

@@ -4,6 +4,7 @@
 
 #include "snlm_device.hpp"
 #include "snlm_sure.hpp"
+#include "snlm_carry.hpp"
 
 namespace snlm {
 

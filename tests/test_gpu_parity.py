@@ -74,6 +74,23 @@ def test_whole_line_sums(ctx, sum):
     check(ctx, img, 10, 3, 200.0, "box", "row_col", sum=sum)
 
 
+@pytest.mark.parametrize("sum", ["plain", "kahan"])
+def test_whole_line_sums_in_segments_keep_bits(ctx, sum):
+    """Whole-line (plain / Kahan) running sums cut into segments that start
+    from the scanned states give bitwise the one-segment result, in both
+    passes (rows 333 long, columns 150 long), FP32 and FP16 input."""
+    img = noisy_image(150, 333, 20.0, seed=14, texture=True)
+    for dtype in ("f32", "f16"):
+        base, _ = run_gpu(ctx, img, 10, 3, 200.0, "box", "row_col", sum=sum, dtype=dtype,
+                          seg_len=1 << 20)
+        for seg in (16, 48, 64, 176):
+            y, _ = run_gpu(ctx, img, 10, 3, 200.0, "box", "row_col", sum=sum, dtype=dtype, seg_len=seg)
+            assert np.array_equal(y, base), (sum, dtype, seg)
+        y, _ = run_gpu(ctx, img, 15, 4, 200.0, "box", "col_row", sum=sum, dtype=dtype, seg_len=32)
+        b2, _ = run_gpu(ctx, img, 15, 4, 200.0, "box", "col_row", sum=sum, dtype=dtype, seg_len=1 << 20)
+        assert np.array_equal(y, b2), (sum, dtype)
+
+
 def test_h_infinite_is_moving_average(ctx):
     img = noisy_image(50, 70, 20.0, seed=9)
     check(ctx, img, 4, 2, math.inf, "box", "row_col")
