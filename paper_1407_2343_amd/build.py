@@ -57,7 +57,7 @@ def build(jobs: int | None = None, only_s=None, verbose: bool = False, increment
     jobs = jobs or int(os.environ.get("SNLM_BUILD_JOBS", "0")) or max(1, os.cpu_count() or 1)
     s_values = list(range(0, 17)) if only_s is None else sorted(set([0] + list(only_s)))
     objs, cmds = [], []
-    dev_deps = [os.path.join(CSRC, f) for f in ("snlm_inst.hip", "snlm_device.hpp", "snlm_registry.hpp")]
+    dev_deps = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".hip"))]
     dev_deps.append(os.path.join(ROOT, "include", "snlm.h"))
     for s in s_values:
         o = os.path.join(BUILD, "snlm_inst_s%d.o" % s)

@@ -7,9 +7,10 @@
 // multiply-adds in the same order, Kahan compensation included) and records
 // its state where each later segment's pre-chunk would otherwise start it
 // afresh.  Segments that start from these states give bitwise the whole-line
-// result.  The offset is a run-time value: the entering and leaving lifted
-// samples come from four streams of the line (positions u+K, u+K+s, u-K-1,
-// u-K-1+s), each read 16 samples at a time.
+// result.  The offset is a run-time value: each lane streams its line's
+// samples (four chunks of 16 in flight) into an LDS ring of the recent scaled
+// samples and reads the four it needs per step (positions u+K, u+K+s, u-K-1,
+// u-K-1+s) from there.
 #pragma once
 
 #include "snlm_device.hpp"
@@ -25,6 +26,9 @@ struct CarryArgs {
 template <int K, bool KAHAN>
 __global__ __launch_bounds__(kLanes) void snlm_carry_kernel(CarryArgs a) {
     constexpr int C = kChunk;
+    constexpr int NPF = 4;     // chunks of samples in flight ahead of the recursion
+    constexpr int RING = 128;  // samples of the line kept per lane (needs 2C + 2K + S + 1)
+    __shared__ float ring[RING * kLanes];  // ring[(position mod RING) * 64 + lane]
     const PassDesc& d = a.pass;
     const int S = a.S;
     const int group = blockIdx.x % d.ngroups;
@@ -38,33 +42,45 @@ __global__ __launch_bounds__(kLanes) void snlm_carry_kernel(CarryArgs a) {
     const long kahan_off = (long)(d.nseg - 1) * S * d.nlines;
     const float alpha = d.alpha;
     float R = 0.0f, Rc = 0.0f;
+    auto xs = [&](int p) -> float { return ring[(p & (RING - 1)) * kLanes + lane]; };
 
-    // fresh window sum at u0 = R0 - C (the first pre-chunk), as box_init
-    {
-        const int u0 = R0 - C;
-        float xa[2 * K + 1], xb[2 * K + 1];
-        io.template load<2 * K + 1>(u0 - K, xa);
-        io.template load<2 * K + 1>(u0 - K + s, xb);
+    // Samples stream through NPF register buffers into the ring.
+    float vb[NPF][C];
+    int issued = R0 - C - K - 1;  // next position to load
+    int taken = issued;           // positions below this are in the ring
 #pragma unroll
-        for (int k = 0; k <= 2 * K; ++k) {
-            const float dd = alpha * xa[k] - alpha * xb[k];
-            R = (k == 0) ? dd * dd : __builtin_fmaf(dd, dd, R);
-        }
+    for (int q = 0; q < NPF; ++q) {
+        io.template load<C>(issued, vb[q]);
+        issued += C;
     }
-    // slides for u = u0 + 1 .. : R(u) = R(u-1) + D(u+K) - D(u-K-1)
+    auto take = [&](int q) {
+#pragma unroll
+        for (int t = 0; t < C; ++t) ring[((taken + t) & (RING - 1)) * kLanes + lane] = alpha * vb[q][t];
+        taken += C;
+        io.template load<C>(issued, vb[q]);
+        issued += C;
+    };
+
+    // fresh window sum at u0 = R0 - C (the first pre-chunk), as box_init: its
+    // samples u0-K .. u0+K+s lie in the first three chunks (2K + s <= 32)
+    const int u0 = R0 - C;
+    take(0);
+    take(1);
+    take(2);
+#pragma unroll
+    for (int k = -K; k <= K; ++k) {
+        const float dd = xs(u0 + k) - xs(u0 + k + s);
+        R = (k == -K) ? dd * dd : __builtin_fmaf(dd, dd, R);
+    }
+    // slides for u = u0 + 1 .. : R(u) = R(u-1) + D(u+K) - D(u-K-1), 16 at a time
     int rec = 0;  // next segment start: (rec + 1) * seg_len, recorded at u = start - C + R0
-    int u = R0 - C + 1;
-    while (rec < d.nseg - 1) {
-        float ea[C], eb[C], la[C], lb[C];
-        io.template load<C>(u + K, ea);
-        io.template load<C>(u + K + s, eb);
-        io.template load<C>(u - K - 1, la);
-        io.template load<C>(u - K - 1 + s, lb);
+    int u = u0 + 1;
+    auto steps = [&]() {
         const int target = (rec + 1) * d.seg_len - C + R0;
 #pragma unroll
         for (int t = 0; t < C; ++t) {
-            const float de = alpha * ea[t] - alpha * eb[t];
-            const float dl = alpha * la[t] - alpha * lb[t];
+            const float de = xs(u + t + K) - xs(u + t + K + s);
+            const float dl = xs(u + t - K - 1) - xs(u + t - K - 1 + s);
             if constexpr (KAHAN) {
                 const float tt = __builtin_fmaf(de, de, -(dl * dl));
                 const float y = tt - Rc;
@@ -74,16 +90,22 @@ __global__ __launch_bounds__(kLanes) void snlm_carry_kernel(CarryArgs a) {
             } else {
                 R = __builtin_fmaf(-dl, dl, __builtin_fmaf(de, de, R));
             }
-            if (u + t == target) {
-                if (active) {
-                    const long at = ((long)rec * S + (s - 1)) * d.nlines + line;
-                    a.carry[at] = R;
-                    if constexpr (KAHAN) a.carry[at + kahan_off] = Rc;
-                }
+            if (u + t == target && active) {
+                const long at = ((long)rec * S + (s - 1)) * d.nlines + line;
+                a.carry[at] = R;
+                if constexpr (KAHAN) a.carry[at + kahan_off] = Rc;
             }
         }
         if (u + C > target) ++rec;  // a chunk holds at most one target (seg_len >= C)
         u += C;
+    };
+    while (rec < d.nseg - 1) {
+#pragma unroll
+        for (int q = 0; q < NPF; ++q) {
+            // buffers are taken in issue order: 3, 0, 1, 2, 3, ...
+            take((q + 3) % NPF);
+            if (rec < d.nseg - 1 && u + C - 1 + K + s < taken) steps();
+        }
     }
 }
 
