@@ -108,3 +108,27 @@ def test_null_context_calls_are_rejected():
     assert lib.snlm_poll(None, 1) == snlm.EINVAL
     assert lib.snlm_destroy(None) == snlm.OK
     assert lib.snlm_create(None, 0, None, None, 0) == snlm.EINVAL
+
+
+def test_sure_and_volume_workspaces():
+    H, W = 100, 37
+    off = snlm.sure_layout(H, W)
+    plane = snlm.workspace_bytes(H, W)
+    assert off[:5] == [k * plane for k in range(5)]
+    assert off[5] == 5 * plane and off[6] > off[5] and off[7] > off[6]
+    assert snlm.sure_workspace_bytes(H, W) == off[7]
+    assert snlm.full_workspace_bytes(H, W) == off[7] + plane
+    assert snlm.sure_workspace_bytes(0, 5) == 0 and snlm.full_workspace_bytes(5, 0) == 0
+    Wp = (W + 15) // 16 * 16
+    assert snlm.workspace3d_bytes(3, H, W) >= 2 * 3 * H * Wp * 4
+    assert snlm.workspace3d_bytes(0, H, W) == 0
+    with pytest.raises(snlm.SnlmError):
+        snlm.sure_layout(0, 3)
+
+
+def test_bilateral_params_follow_the_rules():
+    import oracle
+    for s in (5.0, 15.0, 20.0, 30.0, 50.0):
+        a, b = snlm.bilateral_params(s)
+        ra, rb = oracle.bf_params(s)
+        assert a == pytest.approx(ra, rel=1e-6) and b == pytest.approx(rb, rel=1e-6)
