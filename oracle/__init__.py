@@ -19,6 +19,9 @@ What it computes (Ghosh & Chaudhury, "Fast Separable Non-Local Means"):
 * ``nlm1d_div`` -- 1D NLM with its divergence (Sec. 3.1, Alg. 3, eq. div).
 * ``sure``     -- the SURE-optimal combination of the two orders (Alg. 4).
 * ``snlm3d``   -- the separable NLM of a volume along three axes in turn.
+* kernel ``"gauss_iir"`` -- the Gaussian patch kernel by the recursive filter
+  of Young & van Vliet (Sec. 2.2's pointer), untruncated; ``yvv`` exposes the
+  filter itself.
 * ``bilateral``, ``bf_params``, ``full`` -- the bilateral post-processing of
   eq. BF with its parameter rules, and the whole SNLM[f] (Sec. 3.2, 4.1).
 
@@ -40,9 +43,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCE = os.path.join(_HERE, "snlm_oracle.c")
 _LIB = os.path.join(_HERE, "libsnlm_oracle.so")
 
-BOX, GAUSS = 0, 1
+BOX, GAUSS, GAUSS_IIR = 0, 1, 2
 ROW_COL, COL_ROW = 0, 1
-_KERNELS = {"box": BOX, "gauss": GAUSS, BOX: BOX, GAUSS: GAUSS}
+_KERNELS = {"box": BOX, "gauss": GAUSS, "gauss_iir": GAUSS_IIR, BOX: BOX, GAUSS: GAUSS,
+            GAUSS_IIR: GAUSS_IIR}
 _ORDERS = {"row_col": ROW_COL, "col_row": COL_ROW, ROW_COL: ROW_COL, COL_ROW: COL_ROW}
 
 
@@ -93,6 +97,10 @@ class Oracle:
         lib.snlm_oracle_bf_params.restype = None
         lib.snlm_oracle_snlm3d.argtypes = [dp, L, L, L, I, I, D, I, D, ctypes.POINTER(I), dp, I]
         lib.snlm_oracle_snlm3d.restype = I
+        lib.snlm_oracle_yvv.argtypes = [dp, L, D, dp]
+        lib.snlm_oracle_yvv.restype = None
+        lib.snlm_oracle_iir_d2.argtypes = [dp, L, I, D, dp]
+        lib.snlm_oracle_iir_d2.restype = I
         lib.snlm_oracle_max_threads.argtypes = []
         lib.snlm_oracle_max_threads.restype = I
         self._lib = lib
@@ -204,6 +212,23 @@ class Oracle:
             raise ValueError("oracle rejected the arguments")
         return out
 
+    def yvv(self, seq, beta: float) -> np.ndarray:
+        """The recursive Gaussian (Young & van Vliet) of a finite sequence, with
+        the oracle's steady-state starts; gain 1 (no sqrt(2 pi) beta scale)."""
+        a = np.ascontiguousarray(np.asarray(seq, dtype=np.float64))
+        out = np.empty_like(a)
+        self._lib.snlm_oracle_yvv(_ptr(a), a.size, float(beta), _ptr(out))
+        return out
+
+    def iir_d2(self, x, S: int, beta: float) -> np.ndarray:
+        """Recursive-Gaussian patch distances of a line: out[s - 1, u + S] is
+        the distance between the patches at u and u + s, u in [-S, n)."""
+        a = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+        out = np.empty((S, a.size + S))
+        if self._lib.snlm_oracle_iir_d2(_ptr(a), a.size, S, float(beta), _ptr(out)) != 0:
+            raise ValueError("bad arguments")
+        return out
+
     def bilateral(self, f, sigma_s: float, sigma_r: float, threads: int = 0) -> np.ndarray:
         """Bilateral filter of eq. BF (Sec. 3.2), in float64."""
         fa = np.ascontiguousarray(np.asarray(f, dtype=np.float64))
@@ -275,6 +300,14 @@ def sure(*a, **k):
 
 def snlm3d(*a, **k):
     return load().snlm3d(*a, **k)
+
+
+def yvv(*a, **k):
+    return load().yvv(*a, **k)
+
+
+def iir_d2(*a, **k):
+    return load().iir_d2(*a, **k)
 
 
 def bilateral(*a, **k):

@@ -45,6 +45,7 @@
 
 #define ORACLE_BOX 0
 #define ORACLE_GAUSS 1
+#define ORACLE_GAUSS_IIR 2
 #define ORACLE_ROW_COL 0
 #define ORACLE_COL_ROW 1
 
@@ -95,10 +96,14 @@ static double nlm1d_at(const double *x, long n, long stride, long i, int S, int 
 static int bad_args(long n, int S, int K, double h, int kernel, double beta) {
     if (n < 1 || S < 0 || K < 0) return 1;
     if (!(h > 0.0)) return 1; /* rejects NaN too */
-    if (kernel != ORACLE_BOX && kernel != ORACLE_GAUSS) return 1;
+    if (kernel != ORACLE_BOX && kernel != ORACLE_GAUSS && kernel != ORACLE_GAUSS_IIR) return 1;
     if (kernel == ORACLE_GAUSS && K > 0 && !(beta > 0.0)) return 1;
+    if (kernel == ORACLE_GAUSS_IIR && !(beta >= 0.5)) return 1;
     return 0;
 }
+
+static int nlm1d_iir(const double *x, long n, long stride, int S, double h, double beta, double *y,
+                     long ystride);
 
 /* Patch distance d2(i, j) of a contiguous line, i and j any integers (the line
  * is extended by reflection). */
@@ -113,6 +118,7 @@ double snlm_oracle_patch_d2(const double *x, long n, long i, long j, int K, int 
 int snlm_oracle_nlm1d(const double *x, long n, long stride, int S, int K, double h,
                       int kernel, double beta, double *y, long ystride) {
     if (!x || !y || bad_args(n, S, K, h, kernel, beta)) return -1;
+    if (kernel == ORACLE_GAUSS_IIR) return nlm1d_iir(x, n, stride, S, h, beta, y, ystride);
     for (long i = 0; i < n; ++i)
         y[i * ystride] = nlm1d_at(x, n, stride, i, S, K, h, kernel, beta);
     return 0;
@@ -160,6 +166,7 @@ double snlm_oracle_pixel(const double *f, long H, long W, long ld, int S, int K,
                          double h, int kernel, double beta, int order, long r, long c) {
     if (!f || H < 1 || W < 1 || ld < W || r < 0 || r >= H || c < 0 || c >= W) return NAN;
     if (bad_args(H, S, K, h, kernel, beta) || bad_args(W, S, K, h, kernel, beta)) return NAN;
+    if (kernel == ORACLE_GAUSS_IIR) return NAN; /* its distances are not local */
     int reach = S + K;
     if (order == ORACLE_ROW_COL) {
         /* second pass runs along column c; first pass along rows at column c */
@@ -188,6 +195,114 @@ double snlm_oracle_pixel(const double *f, long H, long W, long ld, int S, int K,
         return v;
     }
     return NAN;
+}
+
+/* ------------------------------------------------------------------------
+ * Recursive Gaussian patch kernel (Sec. 2.2 refers to recursive Gaussian
+ * filters for the Gaussian case): the lifted diagonal D_s is smoothed by the
+ * third-order recursive Gaussian of Young & van Vliet (1995), width beta,
+ * forward then backward, and scaled by sqrt(2 pi) beta so that it stands for
+ * the untruncated sum_k exp(-k^2 / (2 beta^2)) D_s(u + k) (g(0) = 1, as the
+ * exact kernel).  Its cost does not depend on the patch width.
+ *   q  = 0.98711 beta - 0.96330                      (beta >= 2.5)
+ *      = 3.97156 - 4.14554 sqrt(1 - 0.26891 beta)    (0.5 <= beta < 2.5)
+ *   b0 = 1.57825 + 2.44413 q + 1.4281 q^2 + 0.422205 q^3
+ *   b1 = 2.44413 q + 2.85619 q^2 + 1.26661 q^3
+ *   b2 = -(1.4281 q^2 + 1.26661 q^3),  b3 = 0.422205 q^3
+ *   B  = 1 - (b1 + b2 + b3) / b0
+ *   forward   w(v) = B D(v) + (b1 w(v-1) + b2 w(v-2) + b3 w(v-3)) / b0
+ *   backward  y(v) = B w(v) + (b1 y(v+1) + b2 y(v+2) + b3 y(v+3)) / b0
+ * Reading (the paper gives no details): D_s(v) = (x_e(v) - x_e(v+s))^2 over
+ * the reflected line for v in [-L, n + L), L = ceil(6 beta) + S + 3; the
+ * forward pass starts at -L with its three past outputs equal to D_s(-L), the
+ * backward pass at n + L - 1 with its three future outputs equal to
+ * w(n + L - 1) (the steady states of constant input).  beta >= 0.5.
+ * ------------------------------------------------------------------------ */
+static void yvv_coeffs(double beta, double *B, double *b) {
+    double q = beta >= 2.5 ? 0.98711 * beta - 0.96330 : 3.97156 - 4.14554 * sqrt(1.0 - 0.26891 * beta);
+    double q2 = q * q, q3 = q2 * q;
+    b[0] = 1.57825 + 2.44413 * q + 1.4281 * q2 + 0.422205 * q3;
+    b[1] = 2.44413 * q + 2.85619 * q2 + 1.26661 * q3;
+    b[2] = -(1.4281 * q2 + 1.26661 * q3);
+    b[3] = 0.422205 * q3;
+    *B = 1.0 - (b[1] + b[2] + b[3]) / b[0];
+}
+
+/* The recursive Gaussian of a finite sequence (forward then backward, the
+ * steady-state starts above), without the sqrt(2 pi) beta scale. */
+void snlm_oracle_yvv(const double *in, long n, double beta, double *out) {
+    double B, b[4];
+    yvv_coeffs(beta, &B, b);
+    double w1 = in[0], w2 = in[0], w3 = in[0];
+    for (long v = 0; v < n; ++v) {
+        double w = B * in[v] + (b[1] * w1 + b[2] * w2 + b[3] * w3) / b[0];
+        out[v] = w;
+        w3 = w2;
+        w2 = w1;
+        w1 = w;
+    }
+    double y1 = out[n - 1], y2 = out[n - 1], y3 = out[n - 1];
+    for (long v = n - 1; v >= 0; --v) {
+        double y = B * out[v] + (b[1] * y1 + b[2] * y2 + b[3] * y3) / b[0];
+        out[v] = y;
+        y3 = y2;
+        y2 = y1;
+        y1 = y;
+    }
+}
+
+/* Recursive-Gaussian patch distances of one strided line: d2[(s - 1) * (n + S)
+ * + (u + S)] = d2 between the patches at u and u + s, u in [-S, n). */
+static int iir_distances(const double *x, long n, long stride, int S, double beta, double *d2) {
+    long L = (long)ceil(6.0 * beta) + S + 3;
+    long m = n + 2 * L;
+    double *D = (double *)malloc(sizeof(double) * (size_t)m);
+    if (!D) return -1;
+    const double scale = sqrt(2.0 * M_PI) * beta;
+    for (int s = 1; s <= S; ++s) {
+        for (long v = -L; v < n + L; ++v) {
+            double a = x[refl(v, n) * stride] - x[refl(v + s, n) * stride];
+            D[v + L] = a * a;
+        }
+        snlm_oracle_yvv(D, m, beta, D);
+        for (long u = -S; u < n; ++u) d2[(size_t)(s - 1) * (n + S) + (u + S)] = scale * D[u + L];
+    }
+    free(D);
+    return 0;
+}
+
+/* The recursive-Gaussian distances of a contiguous line, laid out as above
+ * (S rows of n + S values). */
+int snlm_oracle_iir_d2(const double *x, long n, int S, double beta, double *d2) {
+    if (!x || !d2 || n < 1 || S < 1 || !(beta >= 0.5)) return -1;
+    return iir_distances(x, n, 1, S, beta, d2);
+}
+
+/* 1D NLM (eq. 1dNLM) with the recursive-Gaussian patch distances. */
+static int nlm1d_iir(const double *x, long n, long stride, int S, double h, double beta, double *y,
+                     long ystride) {
+    double *d2 = (double *)malloc(sizeof(double) * (size_t)(S > 0 ? S : 1) * (size_t)(n + S));
+    if (!d2) return -1;
+    if (S > 0 && iir_distances(x, n, stride, S, beta, d2)) {
+        free(d2);
+        return -1;
+    }
+    for (long i = 0; i < n; ++i) {
+        double P = 0.0, Q = 0.0;
+        for (long j = i - S; j <= i + S; ++j) {
+            double w = 1.0;
+            if (j != i) {
+                long lo = j < i ? j : i, s = j < i ? i - j : j - i;
+                double d = d2[(size_t)(s - 1) * (n + S) + (lo + S)];
+                w = (d == 0.0) ? 1.0 : exp(-d / (h * h));
+            }
+            P += w * x[refl(j, n) * stride];
+            Q += w;
+        }
+        y[i * ystride] = P / Q;
+    }
+    free(d2);
+    return 0;
 }
 
 /* ------------------------------------------------------------------------
@@ -251,6 +366,7 @@ int snlm_oracle_nlm1d_div(const double *x, long n, long stride, int S, int K, do
                           int kernel, double beta, const double *din, long dstride, double *y,
                           long ystride, double *dout, long ostride) {
     if (!x || !y || !dout || bad_args(n, S, K, h, kernel, beta)) return -1;
+    if (kernel == ORACLE_GAUSS_IIR) return -1;
     for (long i = 0; i < n; ++i) {
         double yi, di;
         nlm1d_div_at(x, n, stride, i, S, K, h, kernel, beta, &yi, &di);
@@ -291,6 +407,7 @@ int snlm_oracle_sure(const double *f, long H, long W, long ld, int S, int K, dou
     if (!f || !f_rc || !f_cr || !d_rc || !d_cr || !out || !theta || !stats) return -1;
     if (H < 1 || W < 1 || ld < W || !(sigma >= 0.0)) return -1;
     if (bad_args(H, S, K, h, kernel, beta) || bad_args(W, S, K, h, kernel, beta)) return -1;
+    if (kernel == ORACLE_GAUSS_IIR) return -1;
     size_t npx = (size_t)H * (size_t)W;
     double *mid = (double *)malloc(sizeof(double) * npx);
     double *dmid = (double *)malloc(sizeof(double) * npx);

@@ -414,6 +414,82 @@ def check_bf_limits_and_invariants(orc):
     assert np.array_equal(orc.bilateral(f, 0.3, 40.0), f)
 
 
+# ---- recursive Gaussian patch kernel (Young & van Vliet, cited in Sec. 2.2) ----
+def _yvv_poles(beta):
+    # The published q(sigma) fit and the cubic of the filter's denominator,
+    # b0 z^3 - b1 z^2 - b2 z - b3, whose roots are the causal poles.
+    q = 0.98711 * beta - 0.96330 if beta >= 2.5 else 3.97156 - 4.14554 * math.sqrt(1 - 0.26891 * beta)
+    b0 = 1.57825 + 2.44413 * q + 1.4281 * q * q + 0.422205 * q ** 3
+    b1 = 2.44413 * q + 2.85619 * q * q + 1.26661 * q ** 3
+    b2 = -(1.4281 * q * q + 1.26661 * q ** 3)
+    b3 = 0.422205 * q ** 3
+    return np.roots([b0, -b1, -b2, -b3])
+
+
+def check_iir_filter(orc):
+    """The forward-backward recursion against its closed forms: unit gain
+    (constants and, away from the ends, ramps pass unchanged), a symmetric
+    impulse response whose variance is the poles' 2 sum p / (1 - p)^2 (a causal
+    cascade of geometric responses, run forward and backward), and a shape
+    within the approximation error of the sampled Gaussian."""
+    for beta in (0.5, 1.0, 2.0, 3.0, 8.0):
+        c = orc.yvv(np.full(64, -3.25), beta)
+        assert np.max(np.abs(c + 3.25)) < 1e-12, beta
+        n, mid = 1201, 600
+        imp = np.zeros(n)
+        imp[mid] = 1.0
+        r = orc.yvv(imp, beta)
+        k = np.arange(n) - mid
+        assert np.max(np.abs(r - r[::-1])) < 1e-12, beta
+        assert abs(r.sum() - 1.0) < 1e-10, beta
+        p = _yvv_poles(beta)
+        var = 2.0 * float(np.sum(p / (1 - p) ** 2).real)
+        assert abs(float(np.sum(r * k * k)) - var) < 1e-8 * var, (beta, var)
+        g = np.exp(-k * k / (2 * beta * beta))
+        g /= g.sum()
+        assert np.max(np.abs(r - g)) < (0.06 if beta >= 2 else 0.10) * g.max(), beta
+        ramp = 0.75 * np.arange(n) - 40.0
+        rr = orc.yvv(ramp, beta)
+        assert np.max(np.abs(rr[300:900] - ramp[300:900])) < 1e-9, beta
+
+
+def check_iir_distances(orc, seed: int = 21):
+    """Distances of the recursive kernel: on a ramp of slope a, away from the
+    ends, every lifted difference is a^2 s^2 and the distance is sqrt(2 pi) beta
+    a^2 s^2 (the untruncated Gaussian's mass times it); on a noisy line they
+    stay within the approximation error of the exact FIR distance with the
+    kernel's tails kept (K = 6 beta), and the 1D NLM built on them stays
+    much closer to the exact Gaussian NLM than the box NLM is."""
+    n = 400
+    for beta in (1.0, 3.0):
+        a = -1.7
+        x = a * np.arange(n) + 12.0
+        d = orc.iir_d2(x, 5, beta)
+        for s in range(1, 6):
+            want = math.sqrt(2 * math.pi) * beta * a * a * s * s
+            got = d[s - 1, 5 + 150:5 + 250]
+            assert np.max(np.abs(got - want)) < 1e-9 * want, (beta, s)
+    rng = np.random.default_rng(seed)
+    n = 160
+    t = np.arange(n)
+    x = 100.0 * np.sin(t / 9.0) + 20.0 * rng.standard_normal(n)
+    for beta, S, tol in ((1.0, 4, 0.12), (2.0, 6, 0.05), (4.0, 3, 0.04)):
+        K = int(math.ceil(6 * beta))
+        d = orc.iir_d2(x, S, beta)
+        ref = np.array([[orc.patch_d2(x, u, u + s, K, "gauss", beta) for u in range(-S, n)]
+                        for s in range(1, S + 1)])
+        assert np.max(np.abs(d - ref)) < tol * ref.max(), beta
+        h = 150.0 * math.sqrt(beta)
+        yi = orc.nlm1d(x, S, 0, h, "gauss_iir", beta)
+        yf = orc.nlm1d(x, S, K, h, "gauss", beta)
+        yb = orc.nlm1d(x, S, K, h, "box")
+        assert np.max(np.abs(yi - yf)) < 0.2 * np.max(np.abs(yf - yb)), beta
+    # h = inf: the window mean, whatever the distances; S = 0: identity
+    assert np.max(np.abs(orc.nlm1d(x, 3, 0, math.inf, "gauss_iir", 2.0)
+                         - uniform_filter1d(x, 7, mode="reflect"))) < 1e-10
+    assert np.array_equal(orc.nlm1d(x, 0, 0, 50.0, "gauss_iir", 2.0), x)
+
+
 ALL_CHECKS = [
     check_worked_examples_1d, check_separable_2x2, check_alg1_distances,
     check_difference_lift, check_patchlift_nlm, check_constant, check_h_inf_box_average,
@@ -421,5 +497,5 @@ ALL_CHECKS = [
     check_k0_pixel_filter, check_pixel_matches_full, check_div_finite_difference,
     check_div_limits, check_sure_minimiser, check_sure_chain_and_orders, check_sure_transpose,
     check_sure_tracks_mse, check_bf_rules, check_bf_gaussian_limit, check_bf_limits_and_invariants,
-    check_3d_box_average, check_3d_transpose_and_slices,
+    check_3d_box_average, check_3d_transpose_and_slices, check_iir_filter, check_iir_distances,
 ]

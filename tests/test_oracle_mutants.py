@@ -47,6 +47,16 @@ MUTANTS = {
     "vol_z_stride": ("long stride = ax == 0 ? 1 : (ax == 1 ? W : H * W);",
                      "long stride = ax == 0 ? 1 : (ax == 1 ? W : H);"),
     "vol_y_line_base": ("base = (l / W) * H * W + (l % W);", "base = l;"),
+    "iir_forward_drops_b3": ("(b[1] * w1 + b[2] * w2 + b[3] * w3) / b[0]", "(b[1] * w1 + b[2] * w2) / b[0]"),
+    "iir_backward_taps_swapped": ("(b[1] * y1 + b[2] * y2 + b[3] * y3) / b[0]",
+                                  "(b[3] * y1 + b[2] * y2 + b[1] * y3) / b[0]"),
+    "iir_backward_reads_input": ("double y = B * out[v] +", "double y = B * in[v] +"),
+    "iir_cold_backward_start": ("double y1 = out[n - 1], y2 = out[n - 1], y3 = out[n - 1];",
+                                "double y1 = 0.0, y2 = 0.0, y3 = 0.0;"),
+    "iir_q_branch": ("double q = beta >= 2.5 ?", "double q = beta >= 25.0 ?"),
+    "iir_scale_missing": ("= scale * D[u + L];", "= D[u + L];"),
+    "iir_partner_behind": ("x[refl(v + s, n) * stride];", "x[refl(v - s, n) * stride];"),
+    "iir_pair_index": ("d2[(size_t)(s - 1) * (n + S) + (lo + S)];", "d2[(size_t)(s - 1) * (n + S) + (i + S)];"),
     "vol_passes_not_chained": ("        double *t = a;\n        a = b;\n        b = t;\n", ""),
 }
 
