@@ -14,11 +14,13 @@ variants), the roofline of the batched kernels (device time from HIP events
 on the stream they run on), the serving workload (2000 requests, Poisson
 arrivals, p50/p99 latency and Mpixel/s, against FIFO plain launches), the
 precision variants on a 4096 x 4096 image, the SURE-optimal combination of
-the two orders on a 2048 x 2048 image (``sure_combination``), and the FP64
-oracle timed on the host cores on a bounded sample of the batch
+the two orders on a 2048 x 2048 image (``sure_combination``), the recursive
+Gaussian patch kernel on a 2048 x 2048 image (``recursive_gaussian``), and the
+FP64 oracle timed on the host cores on a bounded sample of the batch
 (``cpu_baseline``).
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-serve] [--no-precision] [--no-sure] [--no-cpu]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-serve] [--no-precision] [--no-sure]
+                    [--no-iir] [--iir-only] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -360,6 +362,42 @@ def sure_combination(torch, snlm, n=2048, sigma=30.0, nsample=6):
     return rec
 
 
+# ------------------------------------------------------- recursive Gaussian --
+def recursive_gaussian(torch, snlm, n=2048, sigma=30.0):
+    """The Gaussian patch kernel by the recursive filter (kernel "gauss_iir")
+    on an n x n image, S=10, h = 10 sigma sqrt(sqrt(2 pi) beta / 7): Mpixel/s
+    at beta = 2 and at beta = 8 (a width the exact FIR, K <= 8, cannot reach),
+    beside the exact FIR at beta = 2 with K = 4 and K = 6; max-abs against the
+    FP64 oracle over the whole image, and the recursive kernel's distance from
+    the exact FIR (its approximation error, not a parity figure)."""
+    import oracle
+    from paper_1407_2343_amd.synth import noisy_image
+    img = noisy_image(n, n, sigma, seed=7001)
+    x = torch.from_numpy(img).to("cuda:0")
+    xr = x.cpu().numpy().astype(np.float64)
+    ctx = snlm.Context(arena_bytes=snlm.workspace_bytes(n, n) + (1 << 20))
+
+    def h_for(beta):
+        return 10.0 * sigma * float(np.sqrt(np.sqrt(2 * np.pi) * beta / 7.0))
+
+    rec = {"image": "%dx%d sigma=%g S=%d row_col" % (n, n, sigma, S)}
+    outs = {}
+    for name, kern, KK, beta in (("iir_beta2", "gauss_iir", 0, 2.0), ("iir_beta8", "gauss_iir", 0, 8.0),
+                                 ("fir_beta2_K4", "gauss", 4, 2.0), ("fir_beta2_K6", "gauss", 6, 2.0)):
+        y = torch.empty_like(x)
+        j = ctx.job_for(x, y, S, KK, h_for(beta), kern, "row_col", "block", beta)
+        ms, _ = time_steps(torch, lambda: ctx.denoise_job(j), 10, 2)
+        outs[name] = y.cpu().numpy().astype(np.float64)
+        rec[name] = {"mpx_per_s": round(n * n / ms / 1e3, 1), "ms": round(ms, 3)}
+    for name, beta in (("iir_beta2", 2.0), ("iir_beta8", 8.0)):
+        ref = oracle.snlm(xr, S, 0, h_for(beta), "gauss_iir", "row_col", beta=beta)
+        rec[name]["max_abs_vs_oracle"] = float(np.max(np.abs(outs[name] - ref)))
+    rec["iir_beta2"]["max_abs_vs_exact_fir_K6"] = float(np.max(np.abs(outs["iir_beta2"] - outs["fir_beta2_K6"])))
+    rec["iir_beta2"]["rms_vs_exact_fir_K6"] = float(np.sqrt(np.mean((outs["iir_beta2"] - outs["fir_beta2_K6"]) ** 2)))
+    ctx.close()
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -369,6 +407,9 @@ def main():
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sure", action="store_true")
+    ap.add_argument("--no-iir", action="store_true")
+    ap.add_argument("--iir-only", action="store_true",
+                    help="run only the recursive-Gaussian section and print it")
     ap.add_argument("--profile-batch", action="store_true",
                     help="only the batched steps (for rocprofv3 kernel traces and counters)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -399,6 +440,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": n}), flush=True)
+        return
+    if a.iir_only:
+        print(json.dumps({"recursive_gaussian": recursive_gaussian(torch, snlm)}), flush=True)
         return
     log("generating the batch workload")
     items = batch_workload(64, 128, 1024, seed=2000)
@@ -494,6 +538,9 @@ def main():
     if not a.no_sure:
         log("sure combination")
         result["sure_combination"] = sure_combination(torch, snlm)
+    if not a.no_iir:
+        log("recursive gaussian")
+        result["recursive_gaussian"] = recursive_gaussian(torch, snlm)
     if not a.no_cpu:
         log("cpu baseline")
         result["cpu_baseline"] = cpu_baseline(items)

@@ -49,7 +49,33 @@ enum {
     SNLM_ECLOSED = -5      /* the context is shutting down */
 };
 
-typedef enum { SNLM_BOX = 0, SNLM_GAUSS = 1 } snlm_kernel;
+/* Patch kernels g of eq. distanceSquared.
+ *   SNLM_BOX        g = 1 on [-K, K], window sums by the recursion of eq. recursion
+ *   SNLM_GAUSS      g(k) = exp(-k^2 / (2 beta^2)) on [-K, K], an exact FIR
+ *   SNLM_GAUSS_IIR  the untruncated Gaussian of width beta approximated by the
+ *                   third-order recursive filter of Young & van Vliet (1995),
+ *                   the recursive Gaussian Sec. 2.2 points to: each lifted
+ *                   diagonal D_s(v) = (x(v) - x(v+s))^2 of the reflected line is
+ *                   filtered forward then backward, starting L = ceil(6 beta) +
+ *                   S + 3 samples beyond each end with the steady state of its
+ *                   first input, and scaled by sqrt(2 pi) beta (g(0) = 1):
+ *                     q  = 0.98711 beta - 0.96330 (beta >= 2.5),
+ *                          3.97156 - 4.14554 sqrt(1 - 0.26891 beta) otherwise
+ *                     b0 = 1.57825 + 2.44413 q + 1.4281 q^2 + 0.422205 q^3
+ *                     b1 = 2.44413 q + 2.85619 q^2 + 1.26661 q^3
+ *                     b2 = -(1.4281 q^2 + 1.26661 q^3),  b3 = 0.422205 q^3
+ *                     w(v) = B D(v) + (b1 w(v-1) + b2 w(v-2) + b3 w(v-3)) / b0,
+ *                     B = 1 - (b1 + b2 + b3) / b0
+ *                   The weight is exp(-d / h^2) of the filtered value d (which
+ *                   can be slightly negative where the response's lobes
+ *                   reach).  Cost per sample is independent of beta; K only
+ *                   sets the default beta = K / 2.  0.5 <= beta <= 256.  Runs
+ *                   in snlm_denoise, snlm_denoise_ex and snlm_denoise3d (other
+ *                   entry points return SNLM_EINVAL); each pass keeps
+ *                   S (n + L + S) FP32 distances per line in a library-owned
+ *                   device buffer (grown on demand, held until snlm_destroy),
+ *                   which must stay below 2 GiB. */
+typedef enum { SNLM_BOX = 0, SNLM_GAUSS = 1, SNLM_GAUSS_IIR = 2 } snlm_kernel;
 typedef enum { SNLM_ROW_COL = 0, SNLM_COL_ROW = 1 } snlm_order;
 typedef enum { SNLM_F32 = 0, SNLM_F16 = 1 } snlm_dtype;
 

@@ -25,7 +25,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libsnlm.so")
 
 OK, PENDING, EINVAL, ENOMEM, EDEVICE, ENOTICKET, ECLOSED = 0, 1, -1, -2, -3, -4, -5
-KERNELS = {"box": 0, "gauss": 1}
+KERNELS = {"box": 0, "gauss": 1, "gauss_iir": 2}
 ORDERS = {"row_col": 0, "col_row": 1}
 SUMS = {"block": 0, "kahan": 1, "plain": 2}
 DTYPES = {"f32": 0, "f16": 1}

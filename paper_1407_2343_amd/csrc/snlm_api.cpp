@@ -210,7 +210,11 @@ void init_registry() {
     });
 }
 
+// Tuning-table key of the recursive-Gaussian pass (it has no entry in fn).
+constexpr int kVarIirKey = snlm::kNumVariants;
+
 int variant_of(const snlm_job& j) {
+    if (j.kernel == SNLM_GAUSS_IIR) return kVarIirKey;
     if (j.kernel == SNLM_GAUSS) return snlm::kVarGauss;
     return j.sum == SNLM_SUM_KAHAN ? snlm::kVarBoxKahan : snlm::kVarBox;
 }
@@ -218,8 +222,10 @@ int variant_of(const snlm_job& j) {
 bool pass_rows(const snlm_job& j, int pass) { return (pass == 0) == (j.order == SNLM_ROW_COL); }
 
 // Kernel of one pass of a job (the row-pass variant when its lines are rows).
+// (The recursive-Gaussian kernel runs its own two kernels: nullptr for S > 0.)
 const void* kernel_fn(const snlm_job& j, int pass) {
     init_registry();
+    if (j.kernel == SNLM_GAUSS_IIR) return j.S == 0 ? g_reg.fn[0][0][0][0] : nullptr;
     return g_reg.fn[j.S][j.K][variant_of(j)][pass_rows(j, pass) ? 1 : 0];
 }
 
@@ -238,6 +244,59 @@ struct ClassKey {
 };
 ClassKey class_of(const snlm_job& j) { return ClassKey{j.S, j.K, variant_of(j), (int)j.order}; }
 
+// ------------------------------------------------ recursive Gaussian kernel --
+double iir_beta(const snlm_job& j) { return j.beta > 0.0f ? (double)j.beta : j.K / 2.0; }
+
+// Samples the recursion runs beyond each end of a line.
+int iir_reach(int S, double beta) { return (int)std::ceil(6.0 * beta) + S + 3; }
+
+// Bytes of the distances of one pass: lines of n samples.
+double iir_dist_bytes(int n, int nlines, int S, double beta) {
+    return (double)S * (n + iir_reach(S, beta) + S) * (double)nlines * 4.0;
+}
+
+// Largest modulus of the recursion's poles, the roots of z^3 - a1 z^2 - a2 z
+// - a3: the real root r lies in (0, 1) (the cubic is -a3 < 0 at 0 and B > 0 at
+// 1), found by bisection; dividing it out leaves z^2 + c1 z + c0.
+double iir_pole_modulus(double a1, double a2, double a3) {
+    auto f = [&](double z) { return ((z - a1) * z - a2) * z - a3; };
+    double lo = 0.0, hi = 1.0;
+    for (int i = 0; i < 200; ++i) {
+        const double mid = 0.5 * (lo + hi);
+        (f(mid) < 0.0 ? lo : hi) = mid;
+    }
+    const double r = 0.5 * (lo + hi);
+    const double c1 = r - a1, c0 = r * c1 - a2;
+    const double disc = c1 * c1 - 4.0 * c0;
+    double rho2;
+    if (disc < 0.0)
+        rho2 = std::sqrt(std::max(c0, 0.0));
+    else
+        rho2 = 0.5 * (std::fabs(c1) + std::sqrt(disc));
+    return std::max(r, rho2);
+}
+
+// Warm-up of a recursion segment: rho^W <= 1e-12.
+int iir_warmup(double a1, double a2, double a3) {
+    const double rho = std::min(iir_pole_modulus(a1, a2, a3), 0.999999);
+    return std::max(16, (int)std::ceil(std::log(1e-12) / std::log(rho)));
+}
+
+// Coefficients of the recursive Gaussian of width beta (Young & van Vliet):
+// B and a_k = b_k / b0.
+void iir_coeffs(double beta, double* B, double* a1, double* a2, double* a3) {
+    const double q = beta >= 2.5 ? 0.98711 * beta - 0.96330 : 3.97156 - 4.14554 * std::sqrt(1.0 - 0.26891 * beta);
+    const double q2 = q * q, q3 = q2 * q;
+    const double b0 = 1.57825 + 2.44413 * q + 1.4281 * q2 + 0.422205 * q3;
+    const double b1 = 2.44413 * q + 2.85619 * q2 + 1.26661 * q3;
+    const double b2 = -(1.4281 * q2 + 1.26661 * q3);
+    const double b3 = 0.422205 * q3;
+    *B = 1.0 - (b1 + b2 + b3) / b0;
+    *a1 = b1 / b0;
+    *a2 = b2 / b0;
+    *a3 = b3 / b0;
+}
+
 // ---------------------------------------------------------------- checking --
 const char* check_job(const snlm_job* j) {
     if (!j) return "job is NULL";
@@ -248,12 +307,20 @@ const char* check_job(const snlm_job* j) {
     if (j->S < 0 || j->S > SNLM_MAX_S) return "S out of range [0, 16]";
     if (j->K < 0 || j->K > SNLM_MAX_K) return "K out of range [0, 8]";
     if (!(j->h > 0.0f)) return "h must be > 0 (NaN rejected)";
-    if (j->kernel != SNLM_BOX && j->kernel != SNLM_GAUSS) return "unknown kernel";
+    if (j->kernel != SNLM_BOX && j->kernel != SNLM_GAUSS && j->kernel != SNLM_GAUSS_IIR)
+        return "unknown kernel";
     if (j->order != SNLM_ROW_COL && j->order != SNLM_COL_ROW) return "unknown order";
     if (j->sum != SNLM_SUM_BLOCK && j->sum != SNLM_SUM_KAHAN && j->sum != SNLM_SUM_PLAIN)
         return "unknown sum mode";
     if (j->seg_len < 0 || j->seg_len % kChunk != 0) return "seg_len must be 0 or a multiple of 16";
     if (std::isnan(j->beta)) return "beta is NaN";
+    if (j->kernel == SNLM_GAUSS_IIR) {
+        const double beta = iir_beta(*j);
+        if (!(beta >= 0.5 && beta <= 256.0)) return "the recursive Gaussian needs 0.5 <= beta <= 256";
+        if (iir_dist_bytes(j->W, j->H, j->S, beta) >= 2147483647.0 ||
+            iir_dist_bytes(j->H, j->W, j->S, beta) >= 2147483647.0)
+            return "recursive-Gaussian distances of a pass exceed 2 GiB";
+    }
     const size_t esz = j->dtype == SNLM_F16 ? 2 : 4;
     const double in_bytes = ((double)(j->H - 1) * j->ld_in + j->W) * esz;
     const double out_bytes = ((double)(j->H - 1) * j->ld_out + j->W) * 4.0;
@@ -468,6 +535,8 @@ struct snlm_ctx {
     uint32_t* d_status = nullptr;  // device-side failure flags of batched launches
     float* d_carry = nullptr;      // segment-start states of whole-line sums (direct launches)
     size_t carry_cap = 0;
+    float* d_iir = nullptr;        // recursive-Gaussian distances of one pass
+    size_t iir_cap = 0;
     std::vector<LaunchSlot> slots;
     std::map<TuneKey, int> tuned;
     std::mutex tune_mu;
@@ -588,8 +657,104 @@ const void* carry_fn_k(int k, bool kahan) {
 }
 const void* carry_fn(int K, bool kahan) { return carry_fn_k<0>(K, kahan); }
 
+// Grows a library-owned device buffer to at least need bytes.  The old one is
+// freed first (hipFree waits for the work that may still use it).
+int ensure_buffer(snlm_ctx* c, float** buf, size_t* cap, size_t need) {
+    if (*cap >= need) return SNLM_OK;
+    if (*buf) HIP_CHECK(c, hipFree(*buf));
+    *buf = nullptr;
+    *cap = 0;
+    HIP_CHECK(c, hipMalloc(buf, need));
+    *cap = need;
+    return SNLM_OK;
+}
+
+// One recursive-Gaussian pass (S >= 1): the forward and backward recursions
+// of every offset, in segments, then the 1D NLM from the distances.  One
+// library-owned buffer holds w (n + L + S positions per offset and line) and
+// the distances (n + S), each region below 2 GiB.
+int iir_pass(snlm_ctx* c, const snlm_job& j, const PassDesc& d, bool rows, hipStream_t st) {
+    const double beta = iir_beta(j);
+    snlm::IirArgs ia;
+    std::memset(&ia, 0, sizeof(ia));
+    ia.pass = d;
+    ia.S = j.S;
+    ia.L = iir_reach(j.S, beta);
+    iir_coeffs(beta, &ia.B, &ia.a1, &ia.a2, &ia.a3);
+    ia.scale = std::sqrt(2.0 * M_PI) * beta;
+    ia.W = (iir_warmup(ia.a1, ia.a2, ia.a3) + kChunk - 1) / kChunk * kChunk;  // chunk-aligned segments
+    ia.seg = std::max(256, (4 * ia.W + 15) / 16 * 16);  // warm-up <= 1/4 of a segment's work
+    const int nvw = d.n + ia.L + j.S, nvd = d.n + j.S;
+    ia.nseg_f = (nvw + ia.seg - 1) / ia.seg;
+    ia.nseg_b = (nvd + ia.seg - 1) / ia.seg;
+    const size_t wb = (size_t)j.S * nvw * d.nlines * sizeof(float);
+    const size_t db = (size_t)j.S * nvd * d.nlines * sizeof(float);
+    if (wb >= 2147483647u) return fail(c, SNLM_EINVAL, "recursive-Gaussian distances of a pass exceed 2 GiB");
+    const size_t w_off = align_up(db, kAlign);
+    const size_t xt_off = w_off + align_up(wb, kAlign);
+    const size_t xtb = rows ? (size_t)d.n * d.nlines * sizeof(float) : 0;
+    int rc = ensure_buffer(c, &c->d_iir, &c->iir_cap, xt_off + xtb);
+    if (rc) return rc;
+    ia.dist = c->d_iir;
+    ia.dist_bytes = (uint32_t)db;
+    ia.w = (float*)((char*)c->d_iir + w_off);
+    ia.w_bytes = (uint32_t)wb;
+    if (rows) {
+        // the forward recursion reads a transposed FP32 copy of the input
+        snlm::IirTransposeArgs ta;
+        std::memset(&ta, 0, sizeof(ta));
+        ta.pass = d;
+        ta.xt = (float*)((char*)c->d_iir + xt_off);
+        ta.xt_bytes = (uint32_t)xtb;
+        void* targs[] = {&ta};
+        HIP_CHECK(c, hipLaunchKernel((const void*)&snlm::snlm_iir_transpose_kernel<snlm::kLanes>,
+                                     dim3(d.ngroups, (d.n + snlm::kLanes - 1) / snlm::kLanes), dim3(snlm::kLanes),
+                                     targs, 0, st));
+        PassDesc& t = ia.pass;
+        t.in = ta.xt;
+        t.in_f16 = 0;
+        t.in_bytes = ta.xt_bytes;
+        t.in_line = 1;
+        t.in_pos = d.nlines;
+        t.split = 0;
+    }
+    void* args[] = {&ia};
+    HIP_CHECK(c, hipLaunchKernel((const void*)&snlm::snlm_iir_fwd_kernel<4>, dim3(d.ngroups * j.S * ia.nseg_f),
+                                 dim3(snlm::kLanes), args, 0, st));
+    HIP_CHECK(c, hipLaunchKernel((const void*)&snlm::snlm_iir_bwd_kernel<kChunk>,
+                                 dim3(d.ngroups * j.S * ia.nseg_b), dim3(snlm::kLanes), args, 0, st));
+    init_registry();
+    snlm::IirNlmArgs na;
+    std::memset(&na, 0, sizeof(na));
+    na.pass = d;
+    na.dist = ia.dist;
+    na.dist_bytes = ia.dist_bytes;
+    na.nv = nvd;
+    void* nargs[] = {&na};
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    if (c->timing) {
+        rc = timing_pair(c, &ev);
+        if (rc) return rc;
+        HIP_CHECK(c, hipEventRecord(ev.first, st));
+    }
+    HIP_CHECK(c, hipLaunchKernel(g_reg.iir[j.S][rows ? 1 : 0], dim3(d.ngroups * d.nseg), dim3(snlm::kLanes), nargs,
+                                 0, st));
+    if (c->timing) {
+        HIP_CHECK(c, hipEventRecord(ev.second, st));
+        c->t_direct.push_back(ev);
+    }
+    return SNLM_OK;
+}
+
 int enqueue_job(snlm_ctx* c, const snlm_job& j, void* mid, hipStream_t st) {
     for (int pass = 0; pass < 2; ++pass) {
+        if (j.kernel == SNLM_GAUSS_IIR && j.S > 0) {
+            PassDesc d;
+            fill_pass(d, j, pass, mid, chosen_seg_len(c, j, pass));
+            int rc = iir_pass(c, j, d, pass_rows(j, pass), st);
+            if (rc) return rc;
+            continue;
+        }
         const void* fn = kernel_fn(j, pass);
         if (!fn) return fail(c, SNLM_EDEVICE, "kernel variant not compiled");
         PassDesc d;
@@ -598,13 +763,8 @@ int enqueue_job(snlm_ctx* c, const snlm_job& j, void* mid, hipStream_t st) {
             // whole-line sums in segments: the segment-start states first
             const bool kahan = j.sum == SNLM_SUM_KAHAN;
             const size_t need = (size_t)(d.nseg - 1) * j.S * d.nlines * (kahan ? 2 : 1) * sizeof(float);
-            if (c->carry_cap < need) {
-                if (c->d_carry) HIP_CHECK(c, hipFree(c->d_carry));
-                c->d_carry = nullptr;
-                c->carry_cap = 0;
-                HIP_CHECK(c, hipMalloc(&c->d_carry, need));
-                c->carry_cap = need;
-            }
+            int rc = ensure_buffer(c, &c->d_carry, &c->carry_cap, need);
+            if (rc) return rc;
             snlm::CarryArgs ca;
             std::memset(&ca, 0, sizeof(ca));
             ca.pass = d;
@@ -1246,6 +1406,7 @@ int snlm_destroy(snlm_ctx* c) {
         }
     if (c->d_status) (void)hipFree(c->d_status);
     if (c->d_carry) (void)hipFree(c->d_carry);
+    if (c->d_iir) (void)hipFree(c->d_iir);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     if (c->ev_out) (void)hipEventDestroy(c->ev_out);
     if (c->work) (void)hipStreamDestroy(c->work);
@@ -1383,6 +1544,7 @@ const char* check_sure(const snlm_job* j, float sigma) {
     const char* why = check_job(j);
     if (why) return why;
     if (j->kernel == SNLM_BOX && j->sum != SNLM_SUM_BLOCK) return "the SURE combination uses block-restarted sums";
+    if (j->kernel == SNLM_GAUSS_IIR) return "the SURE combination does not take the recursive Gaussian kernel";
     if (!(sigma >= 0.0f) || std::isinf(sigma)) return "sigma must be finite and >= 0";
     return nullptr;
 }
@@ -1514,6 +1676,12 @@ int snlm_denoise3d(snlm_ctx* c, const void* img, int ld_in, snlm_dtype dtype, fl
     const double out_b = (((double)D * H - 1) * ld_out + W) * 4.0;
     if (in_b >= 2147483647.0 || out_b >= 2147483647.0 || (double)vol_plane_bytes(D, H, W) >= 2147483647.0)
         return fail(c, SNLM_EINVAL, "volume larger than 2 GiB");
+    if (kernel == SNLM_GAUSS_IIR)
+        for (int axis = 0; axis < 3; ++axis) {
+            const int n = axis == 0 ? W : (axis == 1 ? H : D);
+            if (iir_dist_bytes(n, (int)((long)D * H * W / n), S, iir_beta(j)) >= 2147483647.0)
+                return fail(c, SNLM_EINVAL, "recursive-Gaussian distances of a pass exceed 2 GiB");
+        }
     const char* ib = (const char*)img;
     const char* ob = (const char*)out;
     if (ob < ib + (size_t)in_b && ib < ob + (size_t)out_b) return fail(c, SNLM_EINVAL, "out overlaps img");
@@ -1537,7 +1705,12 @@ int snlm_denoise3d(snlm_ctx* c, const void* img, int ld_in, snlm_dtype dtype, fl
         PassDesc d;
         fill_pass3d(d, *ins[k], *outs[k], D, H, W, axis, j,
                     heuristic_seg_len(groups, n, 4 * std::max(c->num_cu, 1)));
-        const void* fn = g_reg.fn[S][K][variant_of(j)][axis == 0 ? 1 : 0];
+        if (j.kernel == SNLM_GAUSS_IIR && S > 0) {
+            int rc = iir_pass(c, j, d, axis == 0, c->user);
+            if (rc) return rc;
+            continue;
+        }
+        const void* fn = g_reg.fn[S][K][j.kernel == SNLM_GAUSS_IIR ? 0 : variant_of(j)][axis == 0 ? 1 : 0];
         if (!fn) return fail(c, SNLM_EDEVICE, "kernel variant not compiled");
         int rc = launch_direct(c, fn, d, c->user);
         if (rc) return rc;
@@ -1636,6 +1809,8 @@ int snlm_denoise_batch(snlm_ctx* c, const snlm_job* jobs, int n) {
         if (why) return fail(c, SNLM_EINVAL, std::string("job ") + std::to_string(i) + ": " + why);
         if (jobs[i].kernel == SNLM_BOX && jobs[i].sum != SNLM_SUM_BLOCK)
             return fail(c, SNLM_EINVAL, "batched launches use block-restarted sums");
+        if (jobs[i].kernel == SNLM_GAUSS_IIR)
+            return fail(c, SNLM_EINVAL, "batched launches do not take the recursive Gaussian kernel");
         js.push_back(&jobs[i]);
         mids.push_back(c->arena + need);
         need += mid_bytes(jobs[i].H, jobs[i].W);
@@ -1692,6 +1867,7 @@ int snlm_autotune(snlm_ctx* c, const snlm_job* probe, int* best) {
     if (why) return fail(c, SNLM_EINVAL, why);
     if (probe->kernel == SNLM_BOX && probe->sum != SNLM_SUM_BLOCK)
         return fail(c, SNLM_EINVAL, "only block-restarted sums are tiled");
+    if (probe->kernel == SNLM_GAUSS_IIR) return fail(c, SNLM_EINVAL, "the recursive Gaussian kernel is not tuned");
     if (mid_bytes(probe->H, probe->W) > c->arena_bytes) return fail(c, SNLM_ENOMEM, "arena too small");
     HIP_CHECK(c, hipSetDevice(c->device));
     hipEvent_t e0, e1;
@@ -1892,6 +2068,7 @@ int snlm_submit(snlm_ctx* c, const snlm_job* j, uint64_t* ticket) {
     if (why) return fail(c, SNLM_EINVAL, why);
     if (j->kernel == SNLM_BOX && j->sum != SNLM_SUM_BLOCK)
         return fail(c, SNLM_EINVAL, "served jobs use block-restarted sums");
+    if (j->kernel == SNLM_GAUSS_IIR) return fail(c, SNLM_EINVAL, "served jobs do not take the recursive Gaussian kernel");
     const size_t need = snlm_serving_bytes(j->H, j->W, j->dtype);
     if (need > c->arena_bytes) return fail(c, SNLM_ENOMEM, "job can never fit the arena");
     std::lock_guard<std::mutex> lk(c->mu);

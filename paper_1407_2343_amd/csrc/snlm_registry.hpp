@@ -5,6 +5,7 @@
 #include "snlm_device.hpp"
 #include "snlm_sure.hpp"
 #include "snlm_carry.hpp"
+#include "snlm_iir.hpp"
 
 namespace snlm {
 
@@ -13,9 +14,11 @@ enum Variant { kVarBox = 0, kVarBoxKahan = 1, kVarGauss = 2, kNumVariants = 3 };
 // fn[S][K][variant][rows]: rows = 1 is the variant for passes whose lines are
 // contiguous in memory (LDS transpose tiles), rows = 0 for column passes.
 // div[S][K][gauss]: divergence-carrying passes (block-restarted box, or Gauss).
+// iir[S][rows]: the 1D NLM pass from stored recursive-Gaussian distances (S >= 1).
 struct KernelRegistry {
     const void* fn[kMaxS + 1][kMaxK + 1][kNumVariants][2];
     const void* div[kMaxS + 1][kMaxK + 1][2];
+    const void* iir[kMaxS + 1][2];
 };
 
 }  // namespace snlm

@@ -84,6 +84,22 @@ def test_invalid_jobs_rejected(bad, reason):
     assert reason in why
 
 
+def test_recursive_gaussian_rules():
+    ok = lambda **kw: snlm.validate(job(kernel="gauss_iir", **kw))
+    assert ok(beta=0.5)[0] == snlm.OK
+    assert ok(beta=256.0)[0] == snlm.OK
+    assert ok(K=1)[0] == snlm.OK  # default beta = K / 2
+    for kw in (dict(beta=0.49), dict(beta=256.5), dict(K=0)):
+        rc, why = ok(**kw)
+        assert rc == snlm.EINVAL and "0.5 <= beta" in why, kw
+    # S (n + L + S) distances per line, L = ceil(6 beta) + S + 3: a 16000 x
+    # 16000 image at S = 16 needs 16 GiB of them
+    big = dict(img=0x100000, out=0x100000 + 2 * 16000 * 16000 * 4, H=16000, W=16000, S=16, beta=8.0)
+    rc, why = ok(**big)
+    assert rc == snlm.EINVAL and "2 GiB" in why
+    assert snlm.validate(job(**dict(big, kernel="gauss", K=8)))[0] == snlm.OK
+
+
 def test_unknown_enums_rejected():
     j = job()
     j.kernel = 7
