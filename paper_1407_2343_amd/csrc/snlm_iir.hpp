@@ -119,15 +119,17 @@ __device__ __forceinline__ IirWave iir_wave(const PassDesc& d, int nseg) {
 // (W a multiple of 16, so away from the line's start every 16-step block is
 // either all warm-up or all output).  Each lane streams its line's scaled
 // samples through NPF register buffers (16 samples each, issued NPF chunks
-// ahead) into an LDS ring: chunk c (positions vs + 16c ..) lands in slots
-// (16c mod 64) .. + 15, and the chunk in slots 0..15 is also copied to slots
-// 64..79, so a block's 16 + s <= 32 samples sit at consecutive slots.
+// ahead) into an LDS ring of two chunks: chunk c (positions vs + 16c ..)
+// lands in slots (16c mod 32) .. + 15, and the chunk in slots 0..15 is also
+// copied to slots 32..47, so a block's 16 + s <= 32 samples sit at
+// consecutive slots.  A block at v0 reads chunks v0 and v0 + 16; the chunk at
+// v0 + 32 replaces chunk v0 once the block is done.
 // Lanes past the last line repeat the last line's work and store its values
 // to its addresses (the same bits), so no store needs a lane mask.
 template <int NPF>
 __global__ __launch_bounds__(kLanes) void snlm_iir_fwd_kernel(IirArgs a) {
     constexpr int C = kChunk;
-    constexpr int RING = 64;  // slots of distinct positions: [v0, v0 + 48) in use
+    constexpr int RING = 32;  // slots of distinct positions: [v0, v0 + 32) in use
     static_assert(NPF >= 3, "two chunks are taken before the first step, the third in the loop");
     __shared__ float ring[(RING + C) * kLanes];  // ring[slot * 64 + lane]
     const PassDesc& d = a.pass;
@@ -176,12 +178,12 @@ __global__ __launch_bounds__(kLanes) void snlm_iir_fwd_kernel(IirArgs a) {
         issued += C;
     };
     take(0);
-    take(1);  // taken = v0 + 32
+    take(1);  // chunks vs and vs + 16
     int v0 = vs;
     const float dd0 = ring[lane] - ring[s * kLanes + lane];
     double w1 = (double)(dd0 * dd0), w2 = w1, w3 = w1;
     auto fwd16 = [&]() {
-        const int b = (v0 - vs) & (RING - 1);  // 0, 16, 32 or 48
+        const int b = (v0 - vs) & (RING - 1);  // 0 or 16
         const float* rx = ring + b * kLanes + lane;
         const float* ry = rx + s * kLanes;
         const bool all_out = v0 >= out_a && v0 + C <= out_b;
@@ -203,9 +205,11 @@ __global__ __launch_bounds__(kLanes) void snlm_iir_fwd_kernel(IirArgs a) {
     while (v0 < out_b) {
 #pragma unroll
         for (int q = 0; q < NPF; ++q) {
-            // buffers are taken in issue order: 2, 3, .., NPF-1, 0, 1, 2, ...
-            take((q + 2) % NPF);  // taken = v0 + 48
-            if (v0 < out_b) fwd16();
+            if (v0 < out_b) {
+                fwd16();
+                // buffers are taken in issue order: 2, 3, .., NPF-1, 0, 1, 2, ...
+                take((q + 2) % NPF);  // the chunk at the new v0 + 16
+            }
         }
     }
 }
