@@ -406,7 +406,7 @@ def recursive_gaussian(torch, snlm, n=2048, sigma=30.0):
     rec["iir_beta2"]["roofline"] = {
         "bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s", "frac": round(gbs / 8000.0, 4),
         "bytes": int(staged), "bytes_are": "staged: w and distances written and read once, x read twice, y "
-        "written once per pass, plus the row pass's transposed input (5 kernels per pass pair, whole-path time)",
+        "written once per pass, plus the row pass's transposed input (seven launches, whole-path time)",
         "method_min_bytes": int(2 * 8 * n * n)}
     rec["iir_beta2"]["max_abs_vs_exact_fir_K6"] = float(np.max(np.abs(outs["iir_beta2"] - outs["fir_beta2_K6"])))
     rec["iir_beta2"]["rms_vs_exact_fir_K6"] = float(np.sqrt(np.mean((outs["iir_beta2"] - outs["fir_beta2_K6"]) ** 2)))

@@ -683,8 +683,12 @@ int iir_pass(snlm_ctx* c, const snlm_job& j, const PassDesc& d, bool rows, hipSt
     iir_coeffs(beta, &ia.B, &ia.a1, &ia.a2, &ia.a3);
     ia.scale = std::sqrt(2.0 * M_PI) * beta;
     ia.W = (iir_warmup(ia.a1, ia.a2, ia.a3) + kChunk - 1) / kChunk * kChunk;  // chunk-aligned segments
-    ia.seg = std::max(256, (4 * ia.W + 15) / 16 * 16);  // warm-up <= 1/4 of a segment's work
     const int nvw = d.n + ia.L + j.S, nvd = d.n + j.S;
+    // Segments: about 2048 waves per recursion (two per SIMD: each wave is a
+    // serial chain; more segments cost more warm-up reads), but at least 2W
+    // long (warm-up <= 1/3 of a wave's steps).  A function of the job alone.
+    const int per_line = std::max(1, (2048 + d.ngroups * j.S - 1) / (d.ngroups * j.S));
+    ia.seg = std::max(2 * ia.W, ((nvw + per_line - 1) / per_line + kChunk - 1) / kChunk * kChunk);
     ia.nseg_f = (nvw + ia.seg - 1) / ia.seg;
     ia.nseg_b = (nvd + ia.seg - 1) / ia.seg;
     const size_t wb = (size_t)j.S * nvw * d.nlines * sizeof(float);
@@ -708,8 +712,8 @@ int iir_pass(snlm_ctx* c, const snlm_job& j, const PassDesc& d, bool rows, hipSt
         ta.xt_bytes = (uint32_t)xtb;
         void* targs[] = {&ta};
         HIP_CHECK(c, hipLaunchKernel((const void*)&snlm::snlm_iir_transpose_kernel<snlm::kLanes>,
-                                     dim3(d.ngroups, (d.n + snlm::kLanes - 1) / snlm::kLanes), dim3(snlm::kLanes),
-                                     targs, 0, st));
+                                     dim3(d.ngroups, (d.n + snlm::kLanes - 1) / snlm::kLanes),
+                                     dim3(4 * snlm::kLanes), targs, 0, st));
         PassDesc& t = ia.pass;
         t.in = ta.xt;
         t.in_f16 = 0;

@@ -274,8 +274,8 @@ __global__ __launch_bounds__(kLanes) void snlm_iir_bwd_kernel(IirArgs a) {
 // whose lines are contiguous in memory: xt[p * nlines + line] = x(line, p).
 // Reading lines across lanes touches one cache line per lane and sample; the
 // copy lets every offset's forward wave read 64 lines' sample p as one
-// 256-byte row.  Workgroup (one wave): 64 lines x 64 positions through an LDS
-// tile (odd row stride: no bank conflicts either way).
+// 256-byte row.  Workgroup (four waves): 64 lines x 64 positions through an
+// LDS tile (odd row stride: no bank conflicts either way).
 struct IirTransposeArgs {
     PassDesc pass;
     float* xt;
@@ -283,26 +283,25 @@ struct IirTransposeArgs {
 };
 
 template <int NPOS>
-__global__ __launch_bounds__(kLanes) void snlm_iir_transpose_kernel(IirTransposeArgs a) {
+__global__ __launch_bounds__(4 * kLanes) void snlm_iir_transpose_kernel(IirTransposeArgs a) {
     static_assert(NPOS == kLanes, "one position per lane");
     __shared__ float tile[kLanes * (kLanes + 1)];
     const PassDesc& d = a.pass;
     const int lane = threadIdx.x & (kLanes - 1);
+    const int wq = threadIdx.x / kLanes;  // wave q of 4: lines (and then positions) 16 q .. 16 q + 15
     const int line0 = blockIdx.x * kLanes;
     const int p0 = blockIdx.y * NPOS;
     const int p = min(p0 + lane, d.n - 1);
-    // 16 lines' loads in flight at a time, then their LDS writes
+    // 16 lines' loads in flight per wave, then their LDS writes
     auto rows16 = [&](auto load) {
-        for (int i0 = 0; i0 < kLanes; i0 += 16) {
-            float v[16];
+        float v[16];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const LineIO io = make_io<false>(d, min(line0 + i0 + i, d.nlines - 1), 0, nullptr);
-                v[i] = load(io.rin, io.in_base_b + p * io.in_pos_b);
-            }
-#pragma unroll
-            for (int i = 0; i < 16; ++i) tile[(i0 + i) * (kLanes + 1) + lane] = v[i];
+        for (int i = 0; i < 16; ++i) {
+            const LineIO io = make_io<false>(d, min(line0 + 16 * wq + i, d.nlines - 1), 0, nullptr);
+            v[i] = load(io.rin, io.in_base_b + p * io.in_pos_b);
         }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) tile[(16 * wq + i) * (kLanes + 1) + lane] = v[i];
     };
     if (d.in_f16)
         rows16([](__amdgpu_buffer_rsrc_t r, int off) {
@@ -315,8 +314,9 @@ __global__ __launch_bounds__(kLanes) void snlm_iir_transpose_kernel(IirTranspose
     __syncthreads();
     const __amdgpu_buffer_rsrc_t r = make_rsrc(a.xt, a.xt_bytes);
     const int line = line0 + lane;
-    for (int i = 0; i < kLanes && p0 + i < d.n; ++i) {
-        if (line < d.nlines)
+#pragma unroll
+    for (int i = 16 * wq; i < 16 * wq + 16; ++i) {
+        if (p0 + i < d.n && line < d.nlines)
             __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, tile[lane * (kLanes + 1) + i]), r,
                                                   ((p0 + i) * d.nlines + line) * 4, 0, 0);
     }
