@@ -424,6 +424,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sure", action="store_true")
     ap.add_argument("--no-iir", action="store_true")
+    ap.add_argument("--batch-waves", type=int, default=0, metavar="N",
+                    help="use N persistent waves per SIMD for the batch instead of autotuning (counter runs)")
     ap.add_argument("--iir-only", action="store_true",
                     help="run only the recursive-Gaussian section and print it")
     ap.add_argument("--profile-batch", action="store_true",
@@ -473,8 +475,19 @@ def main():
     def step():
         ctx.denoise_jobs(jobs)
 
-    log("autotuning the batched segment length")
-    seg = ctx.autotune_batch(jobs)
+    if a.batch_waves:
+        # a fixed choice, loaded as the autotuner's record for this kernel class
+        import tempfile
+        path = os.path.join(tempfile.gettempdir(), "snlm_batch_waves_%d.json" % os.getpid())
+        with open(path, "w") as f:
+            json.dump({"arch": "gfx950", "entries": [], "batch": [
+                {"bS": S, "K": K, "variant": 0, "order": 0, "waves_per_simd": a.batch_waves}]}, f)
+        ctx.load_tuning(path)
+        os.remove(path)
+        seg = a.batch_waves
+    else:
+        log("autotuning the batched segment length")
+        seg = ctx.autotune_batch(jobs)
     log("batched: warmup + timed")
     ms_step, wall_ms = time_steps(torch, step, a.steps, a.warmup)
     if a.profile_batch:
