@@ -168,6 +168,22 @@ def test_iir_volume(axes):
     ctx.close()
 
 
+def test_iir_extremes():
+    """The widest kernel (beta = 256: one recursion segment per line, the
+    run-in L = 1555 reflecting a 20-sample line many times) at S = 16; S = 0
+    (the identity, bitwise); and a tiny h (every weight but the centre's
+    underflows: the identity up to rounding)."""
+    import torch
+    ctx = _ctx()
+    _check(ctx, _noisy(20, 300, 20.0, 19), 16, 256.0, 6000.0)
+    _check(ctx, _noisy(300, 20, 20.0, 20), 16, 256.0, 6000.0, "col_row")
+    x = torch.from_numpy(_noisy(33, 47, 20.0, 21)).to("cuda:0")
+    y0 = ctx.denoise(x, 0, 0, 100.0, "gauss_iir", beta=2.0, sync=True)
+    assert torch.equal(y0, x)
+    _check(ctx, _noisy(33, 47, 20.0, 22), 6, 2.0, 1e-3)
+    ctx.close()
+
+
 def test_iir_errors():
     import ctypes
     import torch
