@@ -200,6 +200,66 @@ def test_precision_variants_large(dtype, sum):
     ctx.close()
 
 
+def test_bench_batch_workload_sampled():
+    """The benchmark's batch exactly as bench.py times it: 64 FP32 images, H
+    and W log-uniform in [128, 1024] (seed 2000), h = 10 sigma, S=10, K=3, box,
+    row_col, one job array, autotuned persistent waves, replayed launches.
+    Every image checked at 8 pixels (its corners and 4 random ones) against
+    the FP64 oracle computing those pixels one by one; and the whole output of
+    a few images bitwise equal to their plain launches."""
+    import torch
+    import paper_1407_2343_amd as snlm
+    from paper_1407_2343_amd.synth import batch_workload
+    items = batch_workload(64, 128, 1024, seed=2000)
+    xs = [torch.from_numpy(img).to("cuda:0") for img, _ in items]
+    outs = [torch.empty_like(x) for x in xs]
+    ctx = _ctx(sum(snlm.workspace_bytes(*x.shape) for x in xs) + (1 << 20))
+    jobs = snlm.job_array([ctx.job_for(x, o, 10, 3, 10.0 * sig, "box", "row_col")
+                           for x, o, (_, sig) in zip(xs, outs, items)])
+    waves = ctx.autotune_batch(jobs)
+    for _ in range(3):
+        ctx.denoise_jobs(jobs)
+    ctx.sync()
+    say("bench batch: waves per SIMD", waves, "pixels", sum(x.numel() for x in xs))
+    worst = 0.0
+    for i, ((img, sig), o) in enumerate(zip(items, outs)):
+        H, W = img.shape
+        y = o.cpu().numpy()
+        xr = img.astype(np.float64)
+        rng = np.random.default_rng(100 + i)
+        pts = [(0, 0), (0, W - 1), (H - 1, 0), (H - 1, W - 1)] + [
+            (int(rng.integers(0, H)), int(rng.integers(0, W))) for _ in range(4)]
+        for (r, c) in pts:
+            ref = oracle.pixel(xr, r, c, 10, 3, 10.0 * sig, "box", "row_col")
+            worst = max(worst, abs(float(y[r, c]) - ref))
+    say("  sampled max-abs over 512 pixels", worst)
+    assert worst <= TOL
+    for i in (0, 17, 63):
+        alone = ctx.denoise(xs[i], 10, 3, 10.0 * items[i][1], "box", "row_col", sync=True)
+        assert torch.equal(alone, outs[i]), i
+    ctx.close()
+
+
+def test_precision_4096_sampled():
+    """The precision workload at its full size (4096 x 4096, sigma 30, S=15,
+    K=4, box, block-restarted sums, FP32 and FP16 storage): sampled pixels vs
+    the oracle on exactly the values the GPU read."""
+    import torch
+    import paper_1407_2343_amd as snlm
+    n = 4096
+    img = noisy_image(n, n, 30.0, seed=3001)
+    ctx = _ctx(snlm.workspace_bytes(n, n) + (1 << 20))
+    for dtype in ("f32", "f16"):
+        x = torch.from_numpy(img.astype(np.float16 if dtype == "f16" else np.float32)).to("cuda:0")
+        y = ctx.denoise(x, 15, 4, 300.0, "box", "row_col", sync=True).cpu().numpy()
+        xr = x.cpu().numpy().astype(np.float64)
+        worst = max(abs(float(y[r, c]) - oracle.pixel(xr, r, c, 15, 4, 300.0, "box", "row_col"))
+                    for (r, c) in _sample_pixels(n, n, 32, 11))
+        say("precision 4096", dtype, "sampled max-abs", worst)
+        assert worst <= TOL
+    ctx.close()
+
+
 def test_autotune_keeps_bits():
     import torch
     import paper_1407_2343_amd as snlm
