@@ -730,7 +730,10 @@ int iir_pass(snlm_ctx* c, const snlm_job& j, const PassDesc& d, bool rows, hipSt
     init_registry();
     snlm::IirNlmArgs na;
     std::memset(&na, 0, sizeof(na));
-    na.pass = d;
+    // a row pass reads the transposed copy here too: its samples then load
+    // coalesced, and only its outputs go through the LDS tile (rows never use
+    // two-level line addresses, so the outputs' addressing is unchanged)
+    na.pass = rows ? ia.pass : d;
     na.dist = ia.dist;
     na.dist_bytes = ia.dist_bytes;
     na.nv = nvd;
