@@ -673,6 +673,15 @@ int ensure_buffer(snlm_ctx* c, float** buf, size_t* cap, size_t need) {
 // of every offset, in segments, then the 1D NLM from the distances.  One
 // library-owned buffer holds w (n + L + S positions per offset and line) and
 // the distances (n + S), each region below 2 GiB.
+// Bytes of the library-owned buffer one recursive-Gaussian pass uses: the
+// distances, w, and (row passes) the transposed input, each region aligned.
+size_t iir_pass_bytes(const snlm_job& j, const PassDesc& d, bool rows) {
+    const size_t nvw = (size_t)d.n + iir_reach(j.S, iir_beta(j)) + j.S, nvd = (size_t)d.n + j.S;
+    const size_t wb = (size_t)j.S * nvw * d.nlines * sizeof(float);
+    const size_t db = (size_t)j.S * nvd * d.nlines * sizeof(float);
+    return align_up(db, kAlign) + align_up(wb, kAlign) + (rows ? (size_t)d.n * d.nlines * sizeof(float) : 0);
+}
+
 int iir_pass(snlm_ctx* c, const snlm_job& j, const PassDesc& d, bool rows, hipStream_t st) {
     const double beta = iir_beta(j);
     snlm::IirArgs ia;
@@ -697,7 +706,7 @@ int iir_pass(snlm_ctx* c, const snlm_job& j, const PassDesc& d, bool rows, hipSt
     const size_t w_off = align_up(db, kAlign);
     const size_t xt_off = w_off + align_up(wb, kAlign);
     const size_t xtb = rows ? (size_t)d.n * d.nlines * sizeof(float) : 0;
-    int rc = ensure_buffer(c, &c->d_iir, &c->iir_cap, xt_off + xtb);
+    int rc = ensure_buffer(c, &c->d_iir, &c->iir_cap, iir_pass_bytes(j, d, rows));  // = xt_off + xtb
     if (rc) return rc;
     ia.dist = c->d_iir;
     ia.dist_bytes = (uint32_t)db;
@@ -754,6 +763,18 @@ int iir_pass(snlm_ctx* c, const snlm_job& j, const PassDesc& d, bool rows, hipSt
 }
 
 int enqueue_job(snlm_ctx* c, const snlm_job& j, void* mid, hipStream_t st) {
+    if (j.kernel == SNLM_GAUSS_IIR && j.S > 0) {
+        // size the buffer for both passes before either is enqueued (growing
+        // it between them would free memory the first pass still uses)
+        size_t need = 0;
+        for (int pass = 0; pass < 2; ++pass) {
+            PassDesc d;
+            fill_pass(d, j, pass, mid, kChunk);
+            need = std::max(need, iir_pass_bytes(j, d, pass_rows(j, pass)));
+        }
+        int rc = ensure_buffer(c, &c->d_iir, &c->iir_cap, need);
+        if (rc) return rc;
+    }
     for (int pass = 0; pass < 2; ++pass) {
         if (j.kernel == SNLM_GAUSS_IIR && j.S > 0) {
             PassDesc d;
@@ -1704,6 +1725,17 @@ int snlm_denoise3d(snlm_ctx* c, const void* img, int ld_in, snlm_dtype dtype, fl
     VolView dst{out, ld_out, H * ld_out, false, (uint32_t)out_b};
     const VolView* ins[3] = {&src, &t0, &t1};
     const VolView* outs[3] = {&t0, &t1, &dst};
+    if (kernel == SNLM_GAUSS_IIR && S > 0) {
+        // one buffer size for the three passes, before any is enqueued
+        size_t need = 0;
+        for (int k = 0; k < 3; ++k) {
+            PassDesc d;
+            fill_pass3d(d, *ins[k], *outs[k], D, H, W, axes[k], j, kChunk);
+            need = std::max(need, iir_pass_bytes(j, d, axes[k] == 0));
+        }
+        int rc = ensure_buffer(c, &c->d_iir, &c->iir_cap, need);
+        if (rc) return rc;
+    }
     for (int k = 0; k < 3; ++k) {
         const int axis = axes[k];
         const int n = axis == 0 ? W : (axis == 1 ? H : D);
