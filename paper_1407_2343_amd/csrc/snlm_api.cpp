@@ -775,6 +775,19 @@ int enqueue_job(snlm_ctx* c, const snlm_job& j, void* mid, hipStream_t st) {
         int rc = ensure_buffer(c, &c->d_iir, &c->iir_cap, need);
         if (rc) return rc;
     }
+    const bool carried = j.kernel == SNLM_BOX && j.sum != SNLM_SUM_BLOCK && j.S > 0;
+    if (carried) {
+        // likewise the segment-start states of whole-line sums
+        size_t need = 0;
+        for (int pass = 0; pass < 2; ++pass) {
+            PassDesc d;
+            fill_pass(d, j, pass, mid, chosen_seg_len(c, j, pass), true);
+            need = std::max(need, (size_t)(d.nseg - 1) * j.S * d.nlines * (j.sum == SNLM_SUM_KAHAN ? 2 : 1) *
+                                      sizeof(float));
+        }
+        int rc = ensure_buffer(c, &c->d_carry, &c->carry_cap, need);
+        if (rc) return rc;
+    }
     for (int pass = 0; pass < 2; ++pass) {
         if (j.kernel == SNLM_GAUSS_IIR && j.S > 0) {
             PassDesc d;
@@ -787,12 +800,10 @@ int enqueue_job(snlm_ctx* c, const snlm_job& j, void* mid, hipStream_t st) {
         if (!fn) return fail(c, SNLM_EDEVICE, "kernel variant not compiled");
         PassDesc d;
         fill_pass(d, j, pass, mid, chosen_seg_len(c, j, pass), true);
-        if (j.kernel == SNLM_BOX && !d.restart && d.nseg > 1 && j.S > 0) {
+        if (carried && d.nseg > 1) {
             // whole-line sums in segments: the segment-start states first
+            // (buffer sized above for both passes)
             const bool kahan = j.sum == SNLM_SUM_KAHAN;
-            const size_t need = (size_t)(d.nseg - 1) * j.S * d.nlines * (kahan ? 2 : 1) * sizeof(float);
-            int rc = ensure_buffer(c, &c->d_carry, &c->carry_cap, need);
-            if (rc) return rc;
             snlm::CarryArgs ca;
             std::memset(&ca, 0, sizeof(ca));
             ca.pass = d;
