@@ -10,14 +10,16 @@
 // forward over v in [-L, n + L) (its three past outputs starting as D(-L)),
 // then by the same recursion backward over w (its three future outputs
 // starting as w(n + L - 1)); sqrt(2 pi) beta times the result at u is the
-// distance between the patches at u and u+s.  One pass runs three kernels:
-//   snlm_iir_fwd_kernel   w(v) for v in [-S, n + L), in segments (lines that
-//       are contiguous in memory read a transposed copy, snlm_iir_transpose_kernel)
+// distance between the patches at u and u+s.  One pass runs three kernels
+// (four for lines that are contiguous in memory, which first make a
+// transposed copy of their input with snlm_iir_transpose_kernel and read
+// that instead):
+//   snlm_iir_fwd_kernel   w(v) for v in [-S, n + L), in segments
 //   snlm_iir_bwd_kernel   the distances for u in [-S, n), in segments
-//   snlm_iir_nlm_kernel<S>  the 1D NLM of eq. 1dNLM with the weights exp2(-d)
-//       of the stored distances, with the pairing, accumulation order and
-//       pre-chunk of the lifted pass (results do not depend on its segment
-//       length).
+//   snlm_iir_nlm_kernel<S, ROWS>  the 1D NLM of eq. 1dNLM with the weights
+//       exp2(-d) of the stored distances, with the pairing, accumulation
+//       order and pre-chunk of the lifted pass (results do not depend on its
+//       segment length).
 // A segment of either recursion starts W samples before its first output
 // (forward) or after its last (backward), from the steady state of the value
 // found there, or at the line's own start where that comes first.  The
@@ -58,7 +60,7 @@ struct IirArgs {
 };
 
 struct IirNlmArgs {
-    PassDesc pass;        // samples in and out (no LDS tiles)
+    PassDesc pass;        // samples in (a row pass: the transposed copy) and out
     const float* dist;    // distances written by snlm_iir_bwd_kernel for this pass
     uint32_t dist_bytes;
     int32_t nv;           // n + S
@@ -429,8 +431,10 @@ __device__ __forceinline__ void run_segment_dist(const PassDesc& d, const LineIO
 }
 
 // Grid: ngroups * nseg workgroups of one wave, as the direct lifted pass.
-// ROWS: the variant for lines contiguous in memory (LDS transpose tiles for
-// the samples in and the outputs out, as the lifted pass's row variant).
+// ROWS: the variant for lines contiguous in memory (the LDS transpose tile for
+// the outputs, as the lifted pass's row variant; its samples come from the
+// transposed copy, which every lane reads coalesced, so the input tile stays
+// unused).
 template <int S, bool ROWS>
 __global__ __launch_bounds__(kLanes) void snlm_iir_nlm_kernel(IirNlmArgs a) {
     __shared__ __attribute__((aligned(16))) float tiles[ROWS ? kTileIn + kTileOut : 1];
