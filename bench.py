@@ -369,7 +369,8 @@ def recursive_gaussian(torch, snlm, n=2048, sigma=30.0):
     at beta = 2 and at beta = 8 (a width the exact FIR, K <= 8, cannot reach),
     beside the exact FIR at beta = 2 with K = 4 and K = 6; max-abs against the
     FP64 oracle over the whole image, and the recursive kernel's distance from
-    the exact FIR (its approximation error, not a parity figure)."""
+    the exact FIR with taps out to 3 beta at beta = 1, 2, 8/3 (its
+    approximation error, not a parity figure), beside the box kernel's."""
     import oracle
     from paper_1407_2343_amd.synth import noisy_image
     img = noisy_image(n, n, sigma, seed=7001)
@@ -410,6 +411,24 @@ def recursive_gaussian(torch, snlm, n=2048, sigma=30.0):
         "method_min_bytes": int(2 * 8 * n * n)}
     rec["iir_beta2"]["max_abs_vs_exact_fir_K6"] = float(np.max(np.abs(outs["iir_beta2"] - outs["fir_beta2_K6"])))
     rec["iir_beta2"]["rms_vs_exact_fir_K6"] = float(np.sqrt(np.mean((outs["iir_beta2"] - outs["fir_beta2_K6"]) ** 2)))
+    # the approximation error against the exact FIR with taps out to 3 beta,
+    # at the widths the FIR reaches (K <= 8), and the box kernel's distance
+    # from the same FIR for scale
+    approx = {}
+    for beta in (1.0, 2.0, 8.0 / 3.0):
+        KK = min(8, int(np.ceil(3 * beta)))
+        ys = {}
+        for kern, kk, hh in (("gauss_iir", 0, h_for(beta)), ("gauss", KK, h_for(beta)),
+                             ("box", KK, h_for(beta) * float(np.sqrt((2 * KK + 1) / (np.sqrt(2 * np.pi) * beta))))):
+            y = torch.empty_like(x)
+            ctx.denoise_job(ctx.job_for(x, y, S, kk, hh, kern, "row_col", "block", beta))
+            torch.cuda.synchronize()
+            ys[kern] = y.cpu().numpy().astype(np.float64)
+        d_iir, d_box = ys["gauss_iir"] - ys["gauss"], ys["box"] - ys["gauss"]
+        approx["beta_%.3g_K%d" % (beta, KK)] = {
+            "iir_max_abs": round(float(np.max(np.abs(d_iir))), 4), "iir_rms": round(float(np.sqrt(np.mean(d_iir ** 2))), 4),
+            "box_max_abs": round(float(np.max(np.abs(d_box))), 4), "box_rms": round(float(np.sqrt(np.mean(d_box ** 2))), 4)}
+    rec["error_vs_exact_fir"] = approx
     ctx.close()
     return rec
 
