@@ -218,10 +218,13 @@ __global__ __launch_bounds__(kLanes) void snlm_iir_fwd_kernel(IirArgs a) {
 
 // Backward recursion of one segment: distances for u in [a, b), a = -S + k
 // seg, b = min(a + seg, n); the recursion starts at min(b - 1 + W, n + L - 1)
-// and reads w back C positions at a time, one chunk ahead.  Stores as in the
-// forward kernel (no lane masks).
+// and reads w back C positions at a time through NB register buffers, so
+// that NB - 1 chunks stay in flight while one is filtered (the kernel is
+// bound by the bytes in flight: its grid gives only a few waves per SIMD).
+// Stores as in the forward kernel (no lane masks).
 template <int C>
 __global__ __launch_bounds__(kLanes) void snlm_iir_bwd_kernel(IirArgs a) {
+    constexpr int NB = 4;
     const PassDesc& d = a.pass;
     const IirWave wv = iir_wave(d, a.nseg_b);
     const int s = wv.s;
@@ -234,41 +237,42 @@ __global__ __launch_bounds__(kLanes) void snlm_iir_bwd_kernel(IirArgs a) {
     const int out_b = min(out_a + a.seg, d.n);
     const int vtop = min(out_b - 1 + a.W, d.n + a.L - 1);
     double y1 = (double)wio.load(s, vtop), y2 = y1, y3 = y1;
-    float cur[C], nxt[C];
     // w at top, top - 1, .., top - C + 1 (positions below out_a, never used,
-    // read out_a's)
+    // read out_a's).  No branches around the loads or the stores below: the
+    // compiler then counts them and waits only for the chunk it filters.
     auto load16 = [&](int top, float* dst) {
-        if (top - (C - 1) >= out_a) {
-            const int off0 = wio.uoff(s, top);
 #pragma unroll
-            for (int t = 0; t < C; ++t)
-                dst[t] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(wio.r, wio.base_b,
-                                                                                       off0 - t * wio.pos_b, 0));
-        } else {
-#pragma unroll
-            for (int t = 0; t < C; ++t) dst[t] = wio.load(s, max(top - t, out_a));
-        }
+        for (int t = 0; t < C; ++t) dst[t] = wio.load(s, max(top - t, out_a));
     };
-    load16(vtop, cur);
-    for (int top = vtop;; top -= C) {
-        const bool more = top - C >= out_a;
-        if (more) load16(top - C, nxt);
-        const bool all_out = top < out_b && top - (C - 1) >= out_a;
-        const bool none_out = top - (C - 1) >= out_b;
-        const int off0 = dio.uoff(s, top);
+    float buf[NB][C];
 #pragma unroll
-        for (int t = 0; t < C; ++t) {
-            const double y = __builtin_fma(a1, y1, __builtin_fma(a2, y2, __builtin_fma(a3, y3, B * (double)cur[t])));
-            y3 = y2;
-            y2 = y1;
-            y1 = y;
-            if (all_out || (!none_out && top - t >= out_a && top - t < out_b))
+    for (int q = 0; q < NB; ++q) load16(vtop - q * C, buf[q]);
+    int top = vtop;
+    bool more = true;
+    while (more) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            if (!more) break;
+            const int off0 = dio.uoff(s, top);
+#pragma unroll
+            for (int t = 0; t < C; ++t) {
+                const double y =
+                    __builtin_fma(a1, y1, __builtin_fma(a2, y2, __builtin_fma(a3, y3, B * (double)buf[q][t])));
+                y3 = y2;
+                y2 = y1;
+                y1 = y;
+                // positions outside [out_a, out_b) go past the buffer's
+                // extent (its size as the uniform offset: line * 4 + size
+                // stays below 2^32 as both are below 2^31), where the bounds
+                // check drops the store
+                const int so = (top - t >= out_a && top - t < out_b) ? off0 - t * dio.pos_b : (int)a.dist_bytes;
                 __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, (float)(scale * y)), dio.r,
-                                                      dio.base_b, off0 - t * dio.pos_b, 0);
+                                                      dio.base_b, so, 0);
+            }
+            more = top - C >= out_a;
+            if (more) load16(top - NB * C, buf[q]);  // the chunk NB positions on
+            top -= C;
         }
-        if (!more) break;
-#pragma unroll
-        for (int t = 0; t < C; ++t) cur[t] = nxt[t];
     }
 }
 
