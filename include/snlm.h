@@ -301,8 +301,9 @@ int snlm_plan_seg_len(snlm_ctx *ctx, const snlm_job *job, int pass);
  * the graph replay of its persistent kernels) and of each direct
  * pass launch; enable = 0 stops, waits for the recorded events and returns the
  * summed device time of batched launches in *batch_ms (count in *batch_n) and
- * of direct pass launches in *direct_ms (count in *direct_n).  Pointers may be
- * NULL. */
+ * of direct pass launches in *direct_ms (count in *direct_n).  For the
+ * recursive Gaussian kernel a pass's events bracket its NLM launch only (the
+ * recursions before it are not included).  Pointers may be NULL. */
 int snlm_timing(snlm_ctx *ctx, int enable, double *batch_ms, int *batch_n, double *direct_ms,
                 int *direct_n);
 
