@@ -94,6 +94,38 @@ def test_batch_mixed_classes():
     ctx.close()
 
 
+@pytest.mark.parametrize("mode", ["split", "fused"])
+def test_batch_degenerate_shapes(mode):
+    """Degenerate images in one batched launch beside ordinary ones: 1 x 1,
+    single rows and columns, lines shorter than S + K (the reflection wraps
+    several periods), widths that leave a one-sample last chunk and a
+    one-line last group, and an FP16 image with a row pitch.  Each equals its
+    plain launch bitwise and the FP64 oracle within 1e-3."""
+    import torch
+    import paper_1407_2343_amd as snlm
+    shapes = [(1, 1), (1, 300), (257, 1), (3, 2), (7, 13), (65, 17), (17, 65), (129, 64), (64, 129), (200, 201)]
+    ctx = _ctx(64 << 20, mode)
+    jobs, keep = [], []
+    for i, (H, W) in enumerate(shapes):
+        img = noisy_image(H, W, 20.0, seed=700 + i, texture=False)
+        if i == len(shapes) - 1:  # FP16 storage, pitched
+            big = torch.from_numpy(np.pad(img, ((0, 0), (0, 7))).astype(np.float16)).to("cuda:0")
+            x = big[:, :W]
+        else:
+            x = torch.from_numpy(img).to("cuda:0")
+        o = torch.full((H, W), -5.0, device="cuda:0")
+        jobs.append(ctx.job_for(x, o, 10, 3, 200.0, "box", "row_col"))
+        keep.append((x, o))
+    ctx.denoise_jobs(jobs, sync=True)
+    for (x, o), (H, W) in zip(keep, shapes):
+        say("degenerate", mode, (H, W))
+        alone = ctx.denoise(x, 10, 3, 200.0, "box", "row_col", sync=True)
+        assert torch.equal(o, alone), (H, W)
+        ref = oracle.snlm(x.cpu().numpy().astype(np.float64), 10, 3, 200.0, "box", "row_col")
+        assert max_abs(o.cpu().numpy(), ref) <= TOL, (H, W)
+    ctx.close()
+
+
 def test_serving_alone_equals_mix():
     import torch
     import paper_1407_2343_amd as snlm
