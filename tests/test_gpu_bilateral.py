@@ -19,7 +19,7 @@ def _noisy(H, W, sigma, seed):
 
 
 @pytest.mark.parametrize("H,W", [(5, 3), (37, 53), (64, 64), (130, 47)])
-@pytest.mark.parametrize("ss,sr", [(0.3, 30.0), (0.7069, 77.145), (1.0, 30.0), (2.5, math.inf)])
+@pytest.mark.parametrize("ss,sr", [(0.3, 30.0), (0.7069, 77.145), (1.0, 30.0), (2.5, math.inf), (2.95, 60.0)])
 def test_bilateral_parity(H, W, ss, sr):
     import torch
     import paper_1407_2343_amd as snlm

@@ -63,7 +63,8 @@ def _check_against_oracle(ctx, x, S, K, h, sigma, kernel, xr=None):
     return out, theta, ref
 
 
-@pytest.mark.parametrize("S,K,kernel", [(5, 2, "box"), (4, 3, "gauss"), (10, 3, "box")])
+@pytest.mark.parametrize("S,K,kernel", [(5, 2, "box"), (4, 3, "gauss"), (10, 3, "box"), (16, 8, "box"),
+                                         (16, 8, "gauss")])
 def test_sure_parity(S, K, kernel):
     import torch
     sigma = 20.0

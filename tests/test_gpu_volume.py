@@ -33,7 +33,7 @@ def test_volume_parity(shape, axes):
     ctx.close()
 
 
-@pytest.mark.parametrize("kernel,S,K", [("gauss", 8, 3), ("box", 15, 4)])
+@pytest.mark.parametrize("kernel,S,K", [("gauss", 8, 3), ("box", 15, 4), ("box", 16, 8), ("gauss", 16, 8)])
 def test_volume_kernels_f16(kernel, S, K):
     import torch
     import paper_1407_2343_amd as snlm
