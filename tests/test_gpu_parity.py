@@ -166,3 +166,43 @@ def test_pitched_and_unaligned_views(ctx, pad, offset, order):
     # nothing outside the output view was written
     assert float(out_buf[:, 0].abs().max()) == 0.0
     assert float(out_buf[:, 204:].abs().max()) == 0.0
+
+
+def test_largest_image():
+    """The largest square image the library accepts (23168 x 23168 FP32: the
+    padded FP32 intermediate just below 2 GiB, every byte offset of the
+    32-bit buffer addressing in use), S=10, K=3, both orders: pixels at the
+    corners, on the borders and inside, against the oracle run on crops that
+    hold each pixel's whole reach (S + K in both directions, so the crop's
+    own edges are never reflected into the result)."""
+    import torch
+    import paper_1407_2343_amd as snlm
+    n = 23168
+    rc, why = snlm.validate(snlm.make_job(1 << 20, (1 << 20) + 4 * n * n + 4096, n, n, 10, 3, 200.0))
+    assert rc == snlm.OK, why
+    rng = np.random.default_rng(23168)
+    img = (128.0 + 30.0 * rng.standard_normal((n, n), dtype=np.float32)).astype(np.float32)
+    x = torch.from_numpy(img).to("cuda:0")
+    ctx = snlm.Context(arena_bytes=snlm.workspace_bytes(n, n) + (1 << 20))
+    R = 13  # S + K
+    pts = [(0, 0), (0, n - 1), (n - 1, 0), (n - 1, n - 1), (n // 2, 0), (0, n // 2), (n - 1, n // 3),
+           (n // 3, n - 1), (n // 2, n // 2), (12345, 20000), (n - 14, n - 14), (R, R)]
+    for order in ("row_col", "col_row"):
+        y = ctx.denoise(x, 10, 3, 200.0, "box", order, sync=True)
+        rows = torch.tensor([p[0] for p in pts], device="cuda:0")
+        cols = torch.tensor([p[1] for p in pts], device="cuda:0")
+        got = y[rows, cols].cpu().numpy()
+        worst = 0.0
+        for k, (r, c) in enumerate(pts):
+            r0, c0 = max(0, r - R), max(0, c - R)
+            r1, c1 = min(n, r + R + 1), min(n, c + R + 1)
+            # a crop touching an image border must start (or end) there so
+            # that the reflection at that border is the image's own
+            crop = img[r0:r1, c0:c1].astype(np.float64)
+            assert (r0 == 0 or r - r0 == R) and (r1 == n or r1 - 1 - r == R)
+            ref = oracle.pixel(crop, r - r0, c - c0, 10, 3, 200.0, "box", order)
+            worst = max(worst, abs(float(got[k]) - ref))
+        say("largest image", order, "sampled max-abs %.2e" % worst)
+        assert worst <= TOL
+        del y
+    ctx.close()
