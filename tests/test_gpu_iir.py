@@ -184,6 +184,23 @@ def test_iir_extremes():
     ctx.close()
 
 
+def test_iir_largest_buffers():
+    """A 5700 x 5700 image at S = 16, beta = 2: each pass keeps 16 (n + L + 16)
+    forward values per line (2.10 GB, just under the 2 GiB limit of a
+    region) and 16 (n + 16) distances, so the recursions' 32-bit buffer
+    offsets, and the stores the backward pass drops past the distances'
+    end, run near their limit.  The whole output against the oracle."""
+    import torch
+    n = 5700
+    L = 12 + 16 + 3
+    assert 0.97 * 2 ** 31 < 16 * (n + L + 16) * n * 4 < 2 ** 31 - 1
+    rng = np.random.default_rng(5700)
+    img = (128.0 + 30.0 * rng.standard_normal((n, n))).astype(np.float32)
+    ctx = _ctx(1 << 28)
+    _check(ctx, img, 16, 2.0, 300.0)
+    ctx.close()
+
+
 def test_iir_errors():
     import ctypes
     import torch
