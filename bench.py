@@ -459,7 +459,7 @@ def main():
         write_traffic(*a.write_traffic[:4], int(a.write_traffic[4]))
         return
     if a.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(independent images would shard across GPUs with no exchange).", file=sys.stderr)
         sys.exit(2)
 
