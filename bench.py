@@ -115,11 +115,12 @@ def traffic_from_profiles():
     return rec.get("hbm_bytes_per_step")
 
 
-def write_traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_mib, last=6):
+def write_traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_mib, last=6, out_path=None):
     """Writes profiles/traffic_batch.json from four rocprofv3 --pmc counter
     CSVs: FETCH_SIZE and WRITE_SIZE of a --profile-batch run, and the same two
     counters of a --calibrate-copy run of copy_mib MiB.  Each batched launch
-    averages its last `last` dispatches (the timed steps)."""
+    averages its last `last` dispatches (the timed steps).  Returns the
+    record; out_path defaults to profiles/traffic_batch.json."""
     import csv
     from collections import defaultdict
 
@@ -156,9 +157,10 @@ def write_traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_mib
            "fetch_factor": ff, "write_factor": wf, "launches": launches,
            "hbm_bytes_per_step": int(total), "algorithmic_bytes_per_step": int(px * 16),
            "ratio_to_algorithmic": total / (px * 16), "source_sha256": source_sha()}
-    with open(os.path.join(ROOT, "profiles", "traffic_batch.json"), "w") as fo:
+    with open(out_path or os.path.join(ROOT, "profiles", "traffic_batch.json"), "w") as fo:
         json.dump(rec, fo, indent=1)
     print(json.dumps({k: rec[k] for k in ("hbm_bytes_per_step", "ratio_to_algorithmic")}))
+    return rec
 
 
 # ----------------------------------------------------------------- serving --
