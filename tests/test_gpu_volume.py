@@ -79,3 +79,27 @@ def test_volume_errors():
     assert rc == snlm.ENOMEM
     small.close()
     ctx.close()
+
+
+@pytest.mark.parametrize("axes", ["xyz", "zyx"])
+def test_volume_largest(axes):
+    """A volume at the 2 GiB limit (511 x 1024 x 1024 FP32): its z lines
+    reach byte offsets near 2^31.  Every z line carries the same signal f(z),
+    so the x and y passes see constant lines and leave them as they are
+    (every weight is 1), and every (y, x) line of the output must be the 1D
+    NLM of f: checked on the device against the FP64 oracle's 1D result."""
+    import torch
+    import paper_1407_2343_amd as snlm
+    D, H, W = 511, 1024, 1024
+    assert 0.99 * 2 ** 31 < D * H * W * 4 < 2 ** 31 - 1
+    f = (128.0 + 40.0 * np.random.default_rng(511).standard_normal(D)).astype(np.float32)
+    x = torch.from_numpy(f).to("cuda:0").view(D, 1, 1).expand(D, H, W).contiguous()
+    ctx = snlm.Context(arena_bytes=1 << 16)
+    y = ctx.denoise3d(x, 10, 3, 200.0, "box", axes)
+    torch.cuda.synchronize()
+    g = torch.from_numpy(oracle.nlm1d(f.astype(np.float64), 10, 3, 200.0).astype(np.float32)).to("cuda:0")
+    err = float((y - g.view(D, 1, 1)).abs().max())
+    say("largest volume", axes, "max-abs %.2e" % err)
+    assert err <= TOL
+    del x, y
+    ctx.close()
