@@ -308,17 +308,19 @@ static int nlm1d_iir(const double *x, long n, long stride, int S, double h, doub
 /* ------------------------------------------------------------------------
  * SURE-optimal combination of the two orders (Sec. 3.1, Alg. 3 and Alg. 4).
  *
- *   1D NLM with its divergence (Alg. 3, eq. div, Appendix): along with y(i),
- *     P1 = sum_j w x(j),  P2 = sum_j w x(j)^2,  Q = sum_j w          (|j-i| <= S)
- *     T1 = sum w g(i-j),  T2 = sum w g(i-j) x(j),  T3 = sum w g(i-j) x(2i-j),
- *     T4 = sum w g(i-j) x(2i-j) x(j)                                (|j-i| <= K)
- *     y = P1/Q,  T = T1 y x(i) - T2 x(i) - T3 y + T4,
- *     dout(i) = din(i) * (h^2 + 2T + 2(P2 - Q y^2)) / (Q h^2)
- *   (the closing parenthesis the printed listing lacks is placed so that the
- *   expression equals eq. div: 1/W + (2/(h^2 W))(P2 - W y^2) + (2/(h^2 W)) T).
- *   For h = +inf, or h^2 = 0, the limit 1/Q is used.  The formula is the
- *   paper's, i.e. it treats x(j), j != i, as independent of x(i) even where the
- *   reflection at a line end maps j onto i.
+ *   1D NLM with its divergence (eq. div, derived in the Appendix): along with
+ *   y(i) = sum_j w_ij x(j) / W_i, W_i = sum_j w_ij (eq. 1dNLM), the derivative
+ *   dy(i)/dx(i) by the quotient rule of the Appendix (eq. derivfrac),
+ *     dy(i)/dx(i) = (w_ii + sum_j (x(j) - y(i)) dw_ij/dx(i)) / W_i,   w_ii = 1,
+ *   where the chain rule through eq. distanceSquared gives (g(0) = 1)
+ *     dw_ij/dx(i) = (2 w_ij / h^2) [ (x(j) - x(i))
+ *                                    + g(i-j) (x(2i-j) - x(i)) if |i-j| <= K ]
+ *   (the second term: the tap k = i - j of the patch at j sits on x(i)).
+ *   Expanding the sum gives eq. div term by term; Alg. 3 accumulates the
+ *   same quantities in one pass.  dout(i) = din(i) dy(i)/dx(i).  For h = +inf,
+ *   or h^2 = 0, the limit 1/W_i is used.  The formula is the paper's, i.e. it
+ *   treats x(j), j != i, as independent of x(i) even where the reflection at a
+ *   line end maps j onto i.
  *
  *   Alg. 4: delta = 1; rows then columns carry (f_r, delta_r) -> (f_rc,
  *   delta_rc); columns then rows carry (f_c, delta_c) -> (f_cr, delta_cr); the
@@ -332,33 +334,32 @@ static int nlm1d_iir(const double *x, long n, long stride, int S, double h, doub
  * ------------------------------------------------------------------------ */
 static void nlm1d_div_at(const double *x, long n, long stride, long i, int S, int K,
                          double h, int kernel, double beta, double *yi, double *divi) {
-    double P1 = 0.0, P2 = 0.0, Q = 0.0, T1 = 0.0, T2 = 0.0, T3 = 0.0, T4 = 0.0;
     const double xi = x[refl(i, n) * stride];
+    const double h2 = h * h;
+    double wt[2 * S + 1];
+    double P = 0.0, W = 0.0;
     for (long j = i - S; j <= i + S; ++j) {
         double d2 = patch_d2(x, n, stride, i, j, K, kernel, beta);
-        double w = (d2 == 0.0) ? 1.0 : exp(-d2 / (h * h));
-        double xj = x[refl(j, n) * stride];
-        P1 += w * xj;
-        P2 += w * xj * xj;
-        Q += w;
-        long dij = i - j;
-        if (dij >= -K && dij <= K) {
-            double g = tap((int)dij, kernel, beta);
-            double xm = x[refl(2 * i - j, n) * stride];
-            T1 += w * g;
-            T2 += w * g * xj;
-            T3 += w * g * xm;
-            T4 += w * g * xm * xj;
-        }
+        double w = (d2 == 0.0) ? 1.0 : exp(-d2 / h2);
+        wt[j - (i - S)] = w;
+        P += w * x[refl(j, n) * stride];
+        W += w;
     }
-    double y = P1 / Q;
-    double T = T1 * y * xi - T2 * xi - T3 * y + T4;
-    double h2 = h * h;
+    const double y = P / W;
     *yi = y;
-    if (isinf(h) || h2 == 0.0)
-        *divi = 1.0 / Q;
-    else
-        *divi = (h2 + 2.0 * T + 2.0 * (P2 - Q * y * y)) / (Q * h2);
+    if (isinf(h) || h2 == 0.0) {
+        *divi = 1.0 / W;
+        return;
+    }
+    double acc = 0.0; /* sum_j (x(j) - y) dw_ij/dx(i) */
+    for (long j = i - S; j <= i + S; ++j) {
+        const double xj = x[refl(j, n) * stride];
+        double dd = xj - xi; /* the bracket of dw_ij/dx(i) */
+        if (labs(i - j) <= K) dd += tap((int)(i - j), kernel, beta) * (x[refl(2 * i - j, n) * stride] - xi);
+        const double dw = 2.0 * wt[j - (i - S)] / h2 * dd;
+        acc += (xj - y) * dw;
+    }
+    *divi = (1.0 + acc) / W;
 }
 
 /* 1D NLM with divergence of a strided line: y and dout = din * dy(i)/dx(i). */

@@ -250,6 +250,29 @@ def check_div_finite_difference(orc):
             assert abs(fd - d[i]) < 1e-7 * max(1.0, abs(d[i])), (kernel, i, fd, d[i])
 
 
+def check_div_line_ends(orc):
+    """eq. div at every sample, line ends included.  The formula differentiates
+    with respect to x(i) alone and takes every other sample x(j), j != i, as a
+    separate variable, even where the reflection maps j onto i.  That is the
+    derivative of eq. 1dNLM on the explicitly extended line (NumPy's
+    'symmetric' padding, the half-sample reflection) with only the centre copy
+    of x(i) perturbed: the filter at an interior position of the padded array
+    never reflects."""
+    rng = np.random.default_rng(23)
+    x = rng.normal(size=24) * 20 + 100
+    for kernel, S, K, h in (("box", 5, 3, 35.0), ("gauss", 4, 3, 30.0), ("box", 2, 2, 25.0)):
+        _, d = orc.nlm1d_div(x, S, K, h, kernel)
+        R = S + K
+        xe = np.pad(x, R, mode="symmetric")
+        eps = 1e-4
+        for i in list(range(0, R + 1)) + list(range(x.size - R - 1, x.size)):
+            xp, xm = xe.copy(), xe.copy()
+            xp[R + i] += eps
+            xm[R + i] -= eps
+            fd = (orc.nlm1d(xp, S, K, h, kernel)[R + i] - orc.nlm1d(xm, S, K, h, kernel)[R + i]) / (2 * eps)
+            assert abs(fd - d[i]) < 1e-7 * max(1.0, abs(d[i])), (kernel, i, fd, d[i])
+
+
 def check_div_limits(orc):
     """h = inf: y is a (2S+1)-tap average, whose derivative at the centre is
     1/(2S+1); a tiny h makes y the identity (derivative 1); the divergence is
@@ -495,7 +518,7 @@ ALL_CHECKS = [
     check_difference_lift, check_patchlift_nlm, check_constant, check_h_inf_box_average,
     check_h_zero_identity, check_s0_identity, check_flips, check_transpose, check_affine,
     check_k0_pixel_filter, check_pixel_matches_full, check_div_finite_difference,
-    check_div_limits, check_sure_minimiser, check_sure_chain_and_orders, check_sure_transpose,
+    check_div_line_ends, check_div_limits, check_sure_minimiser, check_sure_chain_and_orders, check_sure_transpose,
     check_sure_tracks_mse, check_bf_rules, check_bf_gaussian_limit, check_bf_limits_and_invariants,
     check_3d_box_average, check_3d_transpose_and_slices, check_iir_filter, check_iir_distances,
 ]

@@ -5,11 +5,11 @@ The two routines here reach the same numbers by the other route the paper
 describes, PatchLift (Sec. 2.1-2.2), so that a dropped tap, a wrong index or a
 wrong sign in either shows up as a mismatch:
 
-* ``alg1_distances`` follows Alg. 1 and eq. dist: the products f(i)f(j) of the
-  band B are packed subdiagonal by subdiagonal with K zeros between them
-  (eqs. correspondence and packing_1), the packed sequence is filtered with
-  the patch kernel, and d2 is read off as Vbar(l_ii) + Vbar(l_jj) - 2 Vbar(l_ij)
-  (eqs. lift and dist).  Samples outside [1, N] do not exist in this layout,
+* ``alg1_distances`` computes what Alg. 1 and eq. dist compute: the products
+  f(i)f(j) of the band B sit at the positions eq. packing_1 gives them in the
+  packed sequence (subdiagonals with K zeros between them), the sequence is
+  filtered with the patch kernel, and d2 is read off as Vbar(l_ii) + Vbar(l_jj)
+  - 2 Vbar(l_ij) (eqs. lift and dist).  Samples outside [1, N] do not exist in this layout,
   which amounts to zero extension of the signal.
 * ``difference_lift_distances`` lifts each offset-s diagonal as
   (x(t) - x(t+s))^2 on the reflected extension and sums it over the patch with
@@ -46,32 +46,32 @@ def l_index(i: int, j: int, N: int, S: int, K: int) -> int:
     return num // 2 + j
 
 
+def band(N: int, S: int):
+    """The band B of Sec. 2.1 (eq. band): 1-based pairs (i, j), i >= j,
+    i - j <= S, both inside [1, N]."""
+    return [(j + d, j) for d in range(S + 1) for j in range(1, N - d + 1)]
+
+
 def alg1_vbar(f1: np.ndarray, S: int, K: int, g: np.ndarray):
-    """Alg. 1: pack the subdiagonals of F = f f^T (with K zeros between them)
-    into V and filter with g.  ``f1`` is the signal; returns (V, Vbar, positions)
-    with V/Vbar 1-based (index 0 unused) and positions[(i, j)] = l."""
+    """The packed sequence V of Sec. 2.2 and its filtered version Vbar = V * g.
+
+    Each product F(i, j) = f(i) f(j) of the band B is written at the position
+    eq. packing_1 assigns to it; every other position of the length-L sequence
+    (the K-sample gaps between subdiagonals) stays zero.  ``f1`` is the signal;
+    returns (V, Vbar, positions) with V/Vbar 1-based (index 0 unused) and
+    positions[(i, j)] = l."""
     N = f1.size
-    f = np.concatenate([[np.nan], f1])  # 1-based
     L = packed_length(N, S, K)
-    V = np.zeros(L + 1 + K)  # room for the trailing zeros
+    V = np.zeros(L + 1)
     pos = {}
-    l = 0
-    for mu in range(1, S + 2):
-        for nu in range(1, N - S - 1 + mu + 1):
-            l += 1
-            i, j = S + 1 - mu + nu, nu  # eq. correspondence
-            V[l] = f[i] * f[j]
-            pos[(i, j)] = l
-        l += K
-    assert l == L + K
+    for (i, j) in band(N, S):
+        l = l_index(i, j, N, S, K)
+        V[l] = f1[i - 1] * f1[j - 1]
+        pos[(i, j)] = l
+    # Vbar(t) = sum_k g(k) V(t + k), V zero outside [1, L]: entry t - 1 + K
+    # of the full convolution of V(1..L) with the reversed taps
     Vbar = np.zeros_like(V)
-    for t in range(1, L + 1):
-        acc = 0.0
-        for k in range(-K, K + 1):
-            q = t + k
-            if 1 <= q <= L:
-                acc += g[k + K] * V[q]
-        Vbar[t] = acc
+    Vbar[1:] = np.convolve(V[1:], g[::-1])[K:K + L]
     return V, Vbar, pos
 
 

@@ -28,11 +28,15 @@ MUTANTS = {
     "normaliser_off_by_one": ("return P / Q;", "return P / (Q + 1.0);"),
     "tap_difference_unsquared": ("d2 += tap(k, kernel, beta) * (a - b) * (a - b);",
                                  "d2 += tap(k, kernel, beta) * (a - b);"),
-    "div_T_sign": ("double T = T1 * y * xi - T2 * xi - T3 * y + T4;",
-                   "double T = T1 * y * xi - T2 * xi - T3 * y - T4;"),
-    "div_drops_T": ("(h2 + 2.0 * T + 2.0 * (P2 - Q * y * y))", "(h2 + 2.0 * (P2 - Q * y * y))"),
     "div_mirror_index": ("refl(2 * i - j, n)", "refl(2 * j - i, n)"),
-    "div_P2_from_centre": ("P2 += w * xj * xj;", "P2 += w * xi * xi;"),
+    "div_drops_partner_tap": ("if (labs(i - j) <= K) dd +=", "if (0) dd +="),
+    "div_quotient_sign": ("acc += (xj - y) * dw;", "acc += (y - xj) * dw;"),
+    "div_wii_missing": ("*divi = (1.0 + acc) / W;", "*divi = acc / W;"),
+    "div_factor_two": ("const double dw = 2.0 * wt", "const double dw = wt"),
+    "div_centre_term_sign": ("double dd = xj - xi;", "double dd = xi - xj;"),
+    # a mistake confined to the first and last K samples of a line
+    "div_mirror_clamped_at_ends": ("x[refl(2 * i - j, n) * stride] - xi",
+                                   "x[(2 * i - j < 0 ? 0 : (2 * i - j >= n ? n - 1 : 2 * i - j)) * stride] - xi"),
     "div_not_chained": ("(din ? din[i * dstride] : 1.0) * di", "di"),
     "sure_b_sign": ("double b1 = c1 - sg2 * s1", "double b1 = c1 + sg2 * s1"),
     "sure_second_pass_reads_input": ("div_lines(mid, W, dmid, H, W, 0,", "div_lines(f, ld, dmid, H, W, 0,"),
