@@ -73,25 +73,43 @@ def time_steps(torch, fn, steps, warmup):
     return e0.elapsed_time(e1) / steps, wall / steps * 1e3
 
 
-def cpu_baseline(items, budget_s: float = 12.0):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(items, budget_s: float = 12.0, single_budget_s: float = 6.0):
     """The FP64 oracle on the first images of the batch until ~budget_s of
-    wall time, with every host core."""
+    wall time with every host core, then on the first images again with one
+    thread until ~single_budget_s."""
     import oracle
     orc = oracle.load()
-    px = 0
-    t0 = time.perf_counter()
-    n = 0
-    for img, sig in items:
-        orc.snlm(img.astype(np.float64), S, K, 10.0 * sig, "box", "row_col")
-        px += img.size
-        n += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": round(px / dt / 1e6, 4), "unit": "Mpixel/s", "cores": orc.max_threads(),
-            "kind": "oracle",
+
+    def run(threads, budget):
+        px = n = 0
+        t0 = time.perf_counter()
+        for img, sig in items:
+            orc.snlm(img.astype(np.float64), S, K, 10.0 * sig, "box", "row_col", threads=threads)
+            px += img.size
+            n += 1
+            if time.perf_counter() - t0 > budget:
+                break
+        return px, n, time.perf_counter() - t0
+
+    cores = orc.max_threads()
+    px, n, dt = run(cores, budget_s)
+    px1, n1, dt1 = run(1, single_budget_s)
+    return {"value": round(px / dt / 1e6, 4), "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "single_thread_mpx_per_s": round(px1 / dt1 / 1e6, 4),
             "sample": "first %d of the 64 batch images (%d px), FP64 direct separable NLM, "
-                      "S=10 K=3 box row_col, %.1f s wall" % (n, px, dt)}
+                      "S=10 K=3 box row_col, %.1f s wall on %d threads; single thread: first %d "
+                      "images (%d px), %.1f s" % (n, px, dt, cores, n1, px1, dt1)}
 
 
 def source_sha():
@@ -164,13 +182,17 @@ def write_traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_mib
 
 
 # ----------------------------------------------------------------- serving --
-def serving(torch, snlm, n_req=2000, rate_frac=0.7, seed=4000):
+def serving(torch, snlm, n_req=2000, rate_frac=0.7, seed=4000, check=32):
     """2000 requests (sizes log-uniform 64..2048 per axis, sigma U[10,40],
     S in {5,10,15}, K in {2,3,4}, box/Gauss and both orders 50/50), inputs
-    generated on the device before timing.  Saturation throughput first (all
-    requests at t = 0), then Poisson arrivals at rate_frac of it; p50/p99 of
-    submit-to-completion latency.  Baseline: the same arrivals served FIFO by
-    plain single-image launches, one at a time."""
+    generated on the device before timing and submitted by the library's own
+    request driver (snlm_submit_many).  Saturation throughput first (every
+    request at t = 0), then Poisson arrivals at rate_frac of it; p50/p99 of
+    the device-measured latency (the submit event on the caller's stream to
+    the end of the job's round, both GPU timestamps) and of the host-observed
+    one.  `check` requests are compared bitwise with plain launches of the same
+    job.  Baseline: the same arrivals served FIFO by plain single-image
+    launches, one at a time."""
     from paper_1407_2343_amd.synth import clean_image, serving_requests
     reqs = serving_requests(n_req, seed=seed, rate_per_s=1.0)
     g = torch.Generator(device="cuda:0")
@@ -188,29 +210,29 @@ def serving(torch, snlm, n_req=2000, rate_frac=0.7, seed=4000):
         outs.append(torch.empty((r["H"], r["W"]), dtype=torch.float32, device="cuda:0"))
     torch.cuda.synchronize()
     total_px = sum(r["H"] * r["W"] for r in reqs)
-    arena = 512 << 20  # HBM budget of in-flight intermediates
+    arena = 1 << 30  # HBM budget of in-flight jobs: staged input, intermediate, output slot
     srv = snlm.Context(arena_bytes=arena)
-    jobs = [srv.job_for(x, o, r["S"], r["K"], 10.0 * r["sigma"], r["kernel"], r["order"])
-            for x, o, r in zip(xs, outs, reqs)]
+    job_list = [srv.job_for(x, o, r["S"], r["K"], 10.0 * r["sigma"], r["kernel"], r["order"])
+                for x, o, r in zip(xs, outs, reqs)]
+    jobs = snlm.job_array(job_list)
 
-    def run(arrivals, count):
-        t_start = time.perf_counter()
-        tickets = []
-        for j, a in zip(jobs[:count], arrivals):
-            while time.perf_counter() - t_start < a:
-                pass
-            tickets.append(srv.submit(j))
-        lat, first, last = [], None, None
+    def run(arrivals, sub):
+        t0 = time.perf_counter()
+        tickets = srv.submit_many(sub, arrivals)
+        t_sub = time.perf_counter() - t0
+        host, dev, first, last = [], [], None, None
         pending = list(tickets)
         while pending:
             rest = []
             for t in pending:
                 ts, ta, td = srv.job_times(t)
                 if td > 0:
+                    dms = srv.job_device_ms(t)
                     st = srv.poll(t)
                     if st != snlm.OK:
                         raise RuntimeError("served job failed: %d %s" % (st, srv.last_error()))
-                    lat.append((td - ts) / 1e3)
+                    host.append((td - ts) / 1e3)
+                    dev.append(dms)
                     first = ts if first is None else min(first, ts)
                     last = td if last is None else max(last, td)
                 else:
@@ -218,25 +240,33 @@ def serving(torch, snlm, n_req=2000, rate_frac=0.7, seed=4000):
             pending = rest
             if pending:
                 time.sleep(0.0002)
-        return np.array(lat), (last - first) / 1e6
+        return np.array(host), np.array(dev), (last - first) / 1e6, t_sub
 
-    run([0.0] * 64, 64)  # warm every kernel class once
-    lat_sat, span_sat = run([0.0] * n_req, n_req)
+    run(None, snlm.job_array(job_list[:64]))  # warm every kernel class once
+    _, dev_sat, span_sat, sub_sat = run(None, jobs)
     sat_rate = n_req / span_sat
     rate = rate_frac * sat_rate
     arr_rng = np.random.default_rng(seed + 11)
     arrivals = np.cumsum(arr_rng.exponential(1.0 / rate, n_req))
-    lat, span = run(list(arrivals), n_req)
+    host, dev, span, _ = run(list(arrivals), jobs)
+    torch.cuda.synchronize()
+    # served results against plain launches of the same jobs, bitwise
+    pick = np.random.default_rng(seed + 13).choice(n_req, size=min(check, n_req), replace=False)
+    served = [outs[i].clone() for i in pick]
     srv.close()
+    plain = snlm.Context(arena_bytes=arena)
+    same = True
+    for i, got in zip(pick, served):
+        plain.denoise_job_sync(job_list[i])
+        same = same and bool(torch.equal(outs[i], got))
 
     # FIFO plain launches at the same arrival times
-    plain = snlm.Context(arena_bytes=arena)
-    for j in jobs[:64]:
+    for j in job_list[:64]:
         plain.denoise_job(j)
     plain.sync()
     t_start = time.perf_counter()
     plat = []
-    for j, a in zip(jobs, arrivals):
+    for j, a in zip(job_list, arrivals):
         while time.perf_counter() - t_start < a:
             pass
         plain.denoise_job(j)
@@ -247,12 +277,19 @@ def serving(torch, snlm, n_req=2000, rate_frac=0.7, seed=4000):
     plat = np.array(plat)
     return {
         "requests": n_req, "pixels": int(total_px), "arena_bytes": arena,
+        "admission": "staged input + FP32 intermediate + FP32 output slot per job within the arena",
         "saturation_req_per_s": round(sat_rate, 1),
         "saturation_mpx_per_s": round(total_px / span_sat / 1e6, 1),
+        "saturation_submit_s": round(sub_sat, 4),
+        "saturation_device_p50_ms": round(float(np.percentile(dev_sat, 50)), 3),
         "rate_req_per_s": round(rate, 1),
-        "p50_ms": round(float(np.percentile(lat, 50)), 3),
-        "p99_ms": round(float(np.percentile(lat, 99)), 3),
+        "p50_ms": round(float(np.percentile(dev, 50)), 3),
+        "p99_ms": round(float(np.percentile(dev, 99)), 3),
+        "latency_is": "device: submit event on the caller's stream to the end of the job's round",
+        "host_p50_ms": round(float(np.percentile(host, 50)), 3),
+        "host_p99_ms": round(float(np.percentile(host, 99)), 3),
         "mpx_per_s": round(total_px / span / 1e6, 1),
+        "checked_requests": len(pick), "checked_bitwise_equal_to_plain": same,
         "plain_fifo_p50_ms": round(float(np.percentile(plat, 50)), 3),
         "plain_fifo_p99_ms": round(float(np.percentile(plat, 99)), 3),
         "plain_fifo_mpx_per_s": round(total_px / plain_span / 1e6, 1),
@@ -260,43 +297,44 @@ def serving(torch, snlm, n_req=2000, rate_frac=0.7, seed=4000):
 
 
 # --------------------------------------------------------------- precision --
-def precision(torch, snlm, n=4096, sigma=30.0, nsample=24):
-    """4096 x 4096, sigma 30, S=15, K=4, box: {FP16, FP32 storage} x
-    {block-restarted, plain, Kahan} running sums; max-abs and RMS error at
-    sampled pixels against the FP64 oracle on the values the GPU read, and for
-    FP16 also against the FP32 input before rounding."""
+def precision(torch, snlm, sizes=(2048, 4096), sigma=30.0):
+    """n x n images, sigma 30, S=15, K=4, box, h = 10 sigma: {FP16, FP32
+    storage} x {block-restarted, plain, Kahan} running sums; max-abs and RMS
+    error over every pixel against the FP64 oracle run on the values the GPU
+    read, and for FP16 also against the FP32 input before rounding."""
     import oracle
     from paper_1407_2343_amd.synth import noisy_image
-    img = noisy_image(n, n, sigma, seed=3001)
-    rng = np.random.default_rng(5)
-    pts = [(0, 0), (n - 1, n - 1), (0, n - 1), (n - 1, 0)] + [
-        (int(rng.integers(0, n)), int(rng.integers(0, n))) for _ in range(nsample - 4)]
-    ctx = snlm.Context(arena_bytes=snlm.workspace_bytes(n, n) + (1 << 20))
-    ref32 = None
     out = {}
-    for dtype in ("f32", "f16"):
-        x = torch.from_numpy(img.astype(np.float16 if dtype == "f16" else np.float32)).to("cuda:0")
-        xr = x.cpu().numpy().astype(np.float64)
-        ref = np.array([oracle.pixel(xr, r, c, 15, 4, 10 * sigma, "box", "row_col") for r, c in pts])
-        if dtype == "f32":
-            ref32 = ref
-        for sm in ("block", "plain", "kahan"):
-            y_t = torch.empty((n, n), device="cuda:0")
-            j = ctx.job_for(x, y_t, 15, 4, 10 * sigma, "box", "row_col", sm)
-            ms, _ = time_steps(torch, lambda: ctx.denoise_job(j), 3, 1)
-            y = y_t.cpu().numpy().astype(np.float64)
-            got = np.array([y[r, c] for r, c in pts])
-            e = got - ref
-            rec = {"max_abs": float(np.max(np.abs(e))), "rms": float(np.sqrt(np.mean(e * e))),
-                   "mpx_per_s": round(n * n / ms / 1e3, 1)}
-            if dtype == "f16":
-                e2 = got - ref32
-                rec["max_abs_vs_unrounded"] = float(np.max(np.abs(e2)))
-                rec["rms_vs_unrounded"] = float(np.sqrt(np.mean(e2 * e2)))
-            out["%s_%s" % (dtype, sm)] = rec
-    ctx.close()
-    return {"image": "%dx%d sigma=%g S=15 K=4 box row_col" % (n, n, sigma),
-            "sampled_pixels": len(pts), "variants": out}
+    for n in sizes:
+        img = noisy_image(n, n, sigma, seed=3001 + n)
+        ctx = snlm.Context(arena_bytes=snlm.workspace_bytes(n, n) + (1 << 20))
+        ref32 = None
+        rec_n = {}
+        for dtype in ("f32", "f16"):
+            x = torch.from_numpy(img.astype(np.float16 if dtype == "f16" else np.float32)).to("cuda:0")
+            xr = x.cpu().numpy().astype(np.float64)
+            t0 = time.perf_counter()
+            ref = oracle.snlm(xr, 15, 4, 10 * sigma, "box", "row_col")
+            log("oracle %dx%d %s: %.1f s" % (n, n, dtype, time.perf_counter() - t0))
+            if dtype == "f32":
+                ref32 = ref
+            for sm in ("block", "plain", "kahan"):
+                y_t = torch.empty((n, n), device="cuda:0")
+                j = ctx.job_for(x, y_t, 15, 4, 10 * sigma, "box", "row_col", sm)
+                ms, _ = time_steps(torch, lambda: ctx.denoise_job(j), 3, 1)
+                y = y_t.cpu().numpy().astype(np.float64)
+                e = y - ref
+                rec = {"max_abs": float(np.max(np.abs(e))), "rms": float(np.sqrt(np.mean(e * e))),
+                       "mpx_per_s": round(n * n / ms / 1e3, 1)}
+                if dtype == "f16":
+                    e2 = y - ref32
+                    rec["max_abs_vs_unrounded"] = float(np.max(np.abs(e2)))
+                    rec["rms_vs_unrounded"] = float(np.sqrt(np.mean(e2 * e2)))
+                rec_n["%s_%s" % (dtype, sm)] = rec
+        ctx.close()
+        out["%dx%d" % (n, n)] = rec_n
+    return {"image": "sigma=%g S=15 K=4 box row_col h=10 sigma" % sigma,
+            "pixels_compared": "every pixel of each image", "variants": out}
 
 
 # ----------------------------------------------------------- SURE combination --
@@ -404,13 +442,16 @@ def recursive_gaussian(torch, snlm, n=2048, sigma=30.0):
     L = int(np.ceil(6 * 2.0)) + S + 3
     per_pass = 4 * n * (2 * S * (n + L + S) + 2 * S * (n + S) + 3 * n)
     staged = 2 * per_pass + 8 * n * n
+    method = 2 * 8 * n * n  # x in and y out, per pass
     ms2 = rec["iir_beta2"]["ms"]
-    gbs = staged / (ms2 * 1e-3) / 1e9
+    gbs = method / (ms2 * 1e-3) / 1e9
     rec["iir_beta2"]["roofline"] = {
         "bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s", "frac": round(gbs / 8000.0, 4),
-        "bytes": int(staged), "bytes_are": "staged: w and distances written and read once, x read twice, y "
-        "written once per pass, plus the row pass's transposed input (seven launches, whole-path time)",
-        "method_min_bytes": int(2 * 8 * n * n)}
+        "bytes": int(method), "bytes_are": "the method's own: x in and y out (4 + 4 B per pixel) per pass, "
+        "over the whole-path time (seven launches)",
+        "staged_bytes": int(staged), "staged_gb_per_s": round(staged / (ms2 * 1e-3) / 1e9, 1),
+        "staged_are": "w and distances written and read once, x read twice, y written once per pass, plus "
+        "the row pass's transposed input"}
     rec["iir_beta2"]["max_abs_vs_exact_fir_K6"] = float(np.max(np.abs(outs["iir_beta2"] - outs["fir_beta2_K6"])))
     rec["iir_beta2"]["rms_vs_exact_fir_K6"] = float(np.sqrt(np.mean((outs["iir_beta2"] - outs["fir_beta2_K6"]) ** 2)))
     # the approximation error against the exact FIR with taps out to 3 beta,
@@ -540,8 +581,22 @@ def main():
     for kernel in ("box", "gauss"):
         for order in ("row_col", "col_row"):
             j512 = ctx.job_for(x512, o512, S, K, 200.0, kernel, order)
-            ms, _ = time_steps(torch, lambda: ctx.denoise_job(j512), max(20, a.steps), 3)
-            plain512["%s_%s" % (kernel, order)] = round(512 * 512 / (ms * 1e-3) / 1e6, 1)
+            # device time of each of 60 single launches (both passes), events on
+            # the stream they run on
+            for _ in range(3):
+                ctx.denoise_job(j512)
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(60)]
+            for e0, e1 in evs:
+                e0.record()
+                ctx.denoise_job(j512)
+                e1.record()
+            torch.cuda.synchronize()
+            t = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+            p50, p99 = float(np.percentile(t, 50)), float(np.percentile(t, 99))
+            plain512["%s_%s" % (kernel, order)] = {
+                "mpx_per_s_p50": round(512 * 512 / (p50 * 1e-3) / 1e6, 1),
+                "ms_p50": round(p50, 4), "ms_p99": round(p99, 4), "launches": len(t)}
 
     pairs = total_px * 2 * S
     alg_ops = pairs * PAIR_VALU

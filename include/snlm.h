@@ -46,7 +46,8 @@ enum {
     SNLM_ENOMEM = -2,      /* the job can never fit the arena / table capacity */
     SNLM_EDEVICE = -3,     /* a HIP runtime error or a device-side failure */
     SNLM_ENOTICKET = -4,   /* unknown or already collected ticket */
-    SNLM_ECLOSED = -5      /* the context is shutting down */
+    SNLM_ECLOSED = -5,     /* the context is shutting down */
+    SNLM_EBUSY = -6        /* a direct call while served jobs hold the arena */
 };
 
 /* Patch kernels g of eq. distanceSquared.
@@ -95,7 +96,11 @@ typedef enum {
  * bitwise the same as one segment per line.  Batched and served jobs with
  * these modes keep one segment per line. */
 
-/* Limits of the compiled kernels. */
+/* Limits of the compiled kernels.  S <= 16: a lane walks its line in chunks
+ * of 16 samples, and a segment's first chunk takes the pairs reaching into it
+ * from the one chunk before it (every offset s must fit in that chunk); the
+ * running sums restart every 16 samples.  K <= 8 bounds the registers of the
+ * sample window. */
 #define SNLM_MAX_S 16
 #define SNLM_MAX_K 8
 
@@ -141,24 +146,41 @@ int snlm_create(snlm_ctx **ctx, int device, void *stream, void *arena, size_t ar
  * memory.  NULL is accepted. */
 int snlm_destroy(snlm_ctx *ctx);
 
-/* Arena bytes one job needs for its FP32 intermediate image (synchronous
- * calls), rounded up to 256 bytes. */
+/* Arena bytes one job of a direct call needs for its FP32 intermediate image
+ * (H x Wp, Wp = W rounded up to 16), rounded up to 256 bytes. */
 size_t snlm_workspace_bytes(int H, int W, snlm_dtype dtype);
 
-/* Arena bytes one served job holds while in flight (its FP32 intermediate;
- * input and output stay in the caller's buffers). */
+/* Arena bytes one served job holds while in flight: its staged input (H x W
+ * of the job's dtype), its FP32 intermediate (H x Wp, Wp = W rounded up to
+ * 16) and its FP32 output slot (H x W), each rounded up to 256 bytes. */
 size_t snlm_serving_bytes(int H, int W, snlm_dtype dtype);
 
-/* Separable NLM of one FP32 image with contiguous rows (ld = W).  Enqueued on
- * the context stream; returns once enqueued.  Call snlm_sync for completion.
+/* Arena use.  Direct calls (snlm_denoise*, snlm_enqueue_*, snlm_denoise_sure,
+ * snlm_denoise_full, snlm_denoise3d, the autotuners) place their workspace at
+ * the start of the arena; served jobs take slots anywhere in it.  The two may
+ * not overlap in time: a direct call made while any served job is pending or
+ * in flight returns SNLM_EBUSY, and served jobs start only after the caller's
+ * stream has passed their submit, so after earlier direct calls' kernels.
+ * Direct calls and submits from different threads on one context are not
+ * supported. */
+
+/* Separable NLM of one FP32 image with contiguous rows (ld = W).
+ * Synchronous: returns when out holds the result (the work runs on the
+ * context stream, after work already queued there).
  * Errors: SNLM_EINVAL (NULL pointers, H or W < 1, S or K out of range, h not
  * > 0, unknown kernel/order, out overlapping img), SNLM_ENOMEM (arena smaller
- * than snlm_workspace_bytes), SNLM_EDEVICE. */
+ * than snlm_workspace_bytes), SNLM_EBUSY, SNLM_EDEVICE. */
 int snlm_denoise(snlm_ctx *ctx, const void *img, float *out, int H, int W, int S, int K,
                  float h, int kernel, int order);
 
-/* As snlm_denoise with every option of snlm_job. */
+/* As snlm_denoise with every option of snlm_job.  Synchronous. */
 int snlm_denoise_ex(snlm_ctx *ctx, const snlm_job *job);
+
+/* As snlm_denoise_ex, but returns once the work is enqueued on the context
+ * stream (ordered like any other work on it; snlm_sync or a stream
+ * synchronisation gives completion).  For callers that order work on their own
+ * stream. */
+int snlm_enqueue_ex(snlm_ctx *ctx, const snlm_job *job);
 
 /* Many images in two persistent launches per (S, K, kernel, order) class,
  * captured once in a HIP graph (first-pass launch + second-pass launch)
@@ -166,13 +188,18 @@ int snlm_denoise_ex(snlm_ctx *ctx, const snlm_job *job);
  * are cut at 16-sample boundaries into one equal share of work per persistent
  * workgroup (jobs with seg_len > 0, and box jobs with plain or Kahan sums,
  * keep their segments whole).  The arena must hold the sum of the jobs'
- * snlm_workspace_bytes.  Enqueued on the context stream.  Results are bitwise
+ * snlm_workspace_bytes.  Synchronous.  Results are bitwise
  * identical to snlm_denoise_ex of each job.  Errors as snlm_denoise_ex, plus
  * SNLM_EINVAL for n < 1 and SNLM_ENOMEM when the jobs do not fit the arena
  * together.  With the environment variable SNLM_BATCH_MODE=fused at context
  * creation, a single launch per class instead claims tiles with an atomic
  * counter, second-pass tiles waiting for the first-pass tiles of their image. */
 int snlm_denoise_batch(snlm_ctx *ctx, const snlm_job *jobs, int n);
+
+/* As snlm_denoise_batch, but returns once enqueued on the context stream.  A
+ * batch identical to the previous one (same jobs, arena and tuning) only
+ * replays the captured graphs. */
+int snlm_enqueue_batch(snlm_ctx *ctx, const snlm_job *jobs, int n);
 
 /* SURE-optimal combination of the two orders (Sec. 3.1, Alg. 3 and Alg. 4):
  * out = theta1 f_rc + theta2 f_cr, where f_rc / f_cr are the row_col / col_row
@@ -252,15 +279,34 @@ int snlm_sure_layout(int H, int W, size_t *offsets);
 int snlm_sync(snlm_ctx *ctx);
 
 /* Serving.  Submits a job to the context's scheduler and returns at once with
- * a ticket.  The scheduler admits jobs in arrival order as arena space
- * (snlm_serving_bytes per job: the HBM budget) frees up, runs each round of
- * admitted jobs as batched persistent launches on one of several streams, so
- * that a round overlaps on the device with rounds already running, and
- * writes each result to job->out.  img and out must stay valid until
- * snlm_poll returns non-PENDING.
+ * a ticket.  An event recorded on the context stream at the call orders the
+ * job after work already queued there (img may be written by a kernel still
+ * running on that stream).  The scheduler admits jobs in arrival order while
+ * their snlm_serving_bytes fit what the arena has left (the HBM budget bounds
+ * every byte a served job touches on the device), and runs each round of
+ * admitted jobs on one of several library streams, so that a round overlaps
+ * on the device with rounds already running: one launch copies every input
+ * into its arena slot, the batched persistent launches compute into the
+ * arena output slots, one launch copies the outputs to each job->out.  img
+ * and out must stay valid until snlm_poll returns non-PENDING.
  * Errors: SNLM_EINVAL, SNLM_ENOMEM (the job can never fit the arena),
- * SNLM_ECLOSED. */
+ * SNLM_ECLOSED, SNLM_EDEVICE. */
 int snlm_submit(snlm_ctx *ctx, const snlm_job *job, uint64_t *ticket);
+
+/* Submits jobs[0..n) in order from the calling thread, job i at arrival_us[i]
+ * microseconds (host monotonic clock) after the call (all at once when
+ * arrival_us is NULL), waiting between arrivals; tickets[i] receives each
+ * ticket.  Returns when the last job is submitted, or at the first error
+ * (jobs before it stay submitted).  A request driver that does not depend on
+ * the caller's language runtime. */
+int snlm_submit_many(snlm_ctx *ctx, const snlm_job *jobs, int n, const double *arrival_us,
+                     uint64_t *tickets);
+
+/* Device-side latency of a finished served job: milliseconds between its
+ * submit event on the context stream and the end of its round (outputs
+ * copied), both timestamps taken by the GPU.  -1 if the round failed.
+ * SNLM_ENOTICKET if unknown; call before the final snlm_poll. */
+int snlm_job_device_ms(snlm_ctx *ctx, uint64_t ticket, double *ms);
 
 /* SNLM_PENDING while the job runs; then its final status once (SNLM_OK or an
  * error), after which the ticket is forgotten (SNLM_ENOTICKET). */

@@ -16,7 +16,8 @@ What it computes (Ghosh & Chaudhury, "Fast Separable Non-Local Means"):
 * ``snlm``     -- the separable RC / CR pipelines of Sec. 3.
 * ``pixel``    -- one output pixel of ``snlm``, for sampled checks of large images.
 * ``patch_d2`` -- one patch distance (eq. distanceSquared).
-* ``nlm1d_div`` -- 1D NLM with its divergence (Sec. 3.1, Alg. 3, eq. div).
+* ``nlm1d_div`` -- 1D NLM with its divergence (Sec. 3.1, eq. div, by the
+  quotient rule of the Appendix).
 * ``sure``     -- the SURE-optimal combination of the two orders (Alg. 4).
 * ``snlm3d``   -- the separable NLM of a volume along three axes in turn.
 * kernel ``"gauss_iir"`` -- the Gaussian patch kernel by the recursive filter

@@ -24,7 +24,7 @@ import threading
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libsnlm.so")
 
-OK, PENDING, EINVAL, ENOMEM, EDEVICE, ENOTICKET, ECLOSED = 0, 1, -1, -2, -3, -4, -5
+OK, PENDING, EINVAL, ENOMEM, EDEVICE, ENOTICKET, ECLOSED, EBUSY = 0, 1, -1, -2, -3, -4, -5, -6
 KERNELS = {"box": 0, "gauss": 1, "gauss_iir": 2}
 ORDERS = {"row_col": 0, "col_row": 1}
 SUMS = {"block": 0, "kahan": 1, "plain": 2}
@@ -75,6 +75,11 @@ def lib():
             L.snlm_denoise.argtypes = [vp, vp, vp, i, i, i, i, ctypes.c_float, i, i]
             L.snlm_denoise_ex.argtypes = [vp, jp]
             L.snlm_denoise_batch.argtypes = [vp, jp, i]
+            L.snlm_enqueue_ex.argtypes = [vp, jp]
+            L.snlm_enqueue_batch.argtypes = [vp, jp, i]
+            L.snlm_submit_many.argtypes = [vp, jp, i, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_uint64)]
+            L.snlm_job_device_ms.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]
             L.snlm_sync.argtypes = [vp]
             L.snlm_submit.argtypes = [vp, jp, ctypes.POINTER(ctypes.c_uint64)]
             L.snlm_poll.argtypes = [vp, ctypes.c_uint64]
@@ -118,7 +123,8 @@ def lib():
             L.snlm_last_error.restype = ctypes.c_char_p
             L.snlm_version.restype = ctypes.c_char_p
             for name in ("snlm_create", "snlm_destroy", "snlm_denoise", "snlm_denoise_ex",
-                         "snlm_denoise_batch", "snlm_sync", "snlm_submit", "snlm_poll",
+                         "snlm_denoise_batch", "snlm_enqueue_ex", "snlm_enqueue_batch",
+                         "snlm_submit_many", "snlm_job_device_ms", "snlm_sync", "snlm_submit", "snlm_poll",
                          "snlm_job_times", "snlm_validate", "snlm_autotune", "snlm_autotune_save",
                          "snlm_autotune_load", "snlm_plan_seg_len"):
                 getattr(L, name).restype = ctypes.c_int
@@ -205,8 +211,11 @@ def _check_image(x):
 class Context:
     """A library context bound to one device, one stream and one arena tensor.
 
-    The arena (a uint8 device tensor) holds intermediates of synchronous calls
-    and of served jobs; it grows on demand for the synchronous calls."""
+    The arena (a uint8 device tensor) holds the workspaces of direct calls and
+    the slots of served jobs; it grows on demand for direct calls, but never
+    while served jobs are outstanding (the context would be rebuilt under
+    them).  Calls on a Context are stream-ordered (asynchronous) like PyTorch
+    ops unless they say otherwise."""
 
     def __init__(self, arena_bytes: int = 64 << 20, device: int | None = None, stream=None):
         torch = _torch()
@@ -216,6 +225,7 @@ class Context:
         self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
         self._ptr = ctypes.c_void_p()
         self.arena = None
+        self._tickets = set()
         self._create(max(int(arena_bytes), 256))
 
     def _create(self, nbytes: int):
@@ -231,6 +241,9 @@ class Context:
 
     def ensure_arena(self, nbytes: int):
         if self.arena is None or self.arena.numel() < nbytes:
+            if self._tickets:
+                raise SnlmError(EBUSY, "the arena cannot grow while %d served jobs are outstanding"
+                                % len(self._tickets))
             self._create(nbytes)
 
     @property
@@ -252,6 +265,7 @@ class Context:
         if self._ptr.value:
             lib().snlm_destroy(self._ptr)
             self._ptr = ctypes.c_void_p()
+            self._tickets = set()
 
     def __del__(self):
         try:
@@ -275,7 +289,7 @@ class Context:
             out = torch.empty((H, W), dtype=torch.float32, device=x.device)
         self.ensure_arena(workspace_bytes(H, W))
         job = self.job_for(x, out, S, K, h, kernel, order, sum, beta, seg_len)
-        self.check(lib().snlm_denoise_ex(self._ptr, ctypes.byref(job)), "snlm_denoise_ex")
+        self.check(lib().snlm_enqueue_ex(self._ptr, ctypes.byref(job)), "snlm_enqueue_ex")
         if sync:
             self.sync()
         return out
@@ -355,7 +369,12 @@ class Context:
         return out
 
     def denoise_job(self, job: Job):
-        """Plain launch of a prepared ``Job`` (snlm_denoise_ex)."""
+        """Plain launch of a prepared ``Job``, stream-ordered (snlm_enqueue_ex)."""
+        self.check(lib().snlm_enqueue_ex(self._ptr, ctypes.byref(job)), "snlm_enqueue_ex")
+
+    def denoise_job_sync(self, job: Job):
+        """Plain launch of a prepared ``Job`` that returns with the result in
+        place (snlm_denoise_ex)."""
         self.check(lib().snlm_denoise_ex(self._ptr, ctypes.byref(job)), "snlm_denoise_ex")
 
     def denoise_batch(self, xs, S: int, K: int, hs, kernel="box", order="row_col", beta=None,
@@ -372,7 +391,7 @@ class Context:
         arr = (Job * len(xs))()
         for i, (x, o, h) in enumerate(zip(xs, outs, hs)):
             arr[i] = self.job_for(x, o, S, K, h, kernel, order, "block", beta, 0)
-        self.check(lib().snlm_denoise_batch(self._ptr, arr, len(xs)), "snlm_denoise_batch")
+        self.check(lib().snlm_enqueue_batch(self._ptr, arr, len(xs)), "snlm_enqueue_batch")
         if sync:
             self.sync()
         return outs
@@ -381,9 +400,14 @@ class Context:
         """Batched launch over prepared ``Job`` structures (a list, or a ctypes
         array built once with ``job_array``)."""
         arr = jobs if isinstance(jobs, ctypes.Array) else job_array(jobs)
-        self.check(lib().snlm_denoise_batch(self._ptr, arr, len(arr)), "snlm_denoise_batch")
+        self.check(lib().snlm_enqueue_batch(self._ptr, arr, len(arr)), "snlm_enqueue_batch")
         if sync:
             self.sync()
+
+    def denoise_jobs_sync(self, jobs):
+        """Batched launch that returns with every result in place (snlm_denoise_batch)."""
+        arr = jobs if isinstance(jobs, ctypes.Array) else job_array(jobs)
+        self.check(lib().snlm_denoise_batch(self._ptr, arr, len(arr)), "snlm_denoise_batch")
 
     def autotune(self, x, S, K, h, kernel="box", order="row_col") -> int:
         torch = _torch()
@@ -426,10 +450,38 @@ class Context:
     def submit(self, job: Job) -> int:
         t = ctypes.c_uint64()
         self.check(lib().snlm_submit(self._ptr, ctypes.byref(job), ctypes.byref(t)), "snlm_submit")
+        self._tickets.add(t.value)
         return t.value
 
+    def submit_many(self, jobs, arrivals_s=None) -> list:
+        """Submits prepared jobs from the library's own loop, job i at
+        arrivals_s[i] seconds after the call (all at once when None)."""
+        arr = jobs if isinstance(jobs, ctypes.Array) else job_array(jobs)
+        n = len(arr)
+        tickets = (ctypes.c_uint64 * n)()
+        at = None
+        if arrivals_s is not None:
+            at = (ctypes.c_double * n)(*[float(a) * 1e6 for a in arrivals_s])
+        rc = lib().snlm_submit_many(self._ptr, arr, n, at, tickets)
+        got = [t for t in tickets if t]
+        self._tickets.update(got)
+        self.check(rc, "snlm_submit_many")
+        return list(tickets)
+
     def poll(self, ticket: int) -> int:
-        return lib().snlm_poll(self._ptr, ctypes.c_uint64(ticket))
+        rc = lib().snlm_poll(self._ptr, ctypes.c_uint64(ticket))
+        if rc != PENDING:
+            self._tickets.discard(ticket)
+        return rc
+
+    def job_device_ms(self, ticket: int) -> float:
+        """Device-measured latency of a finished served job (submit event to
+        the end of its round), in milliseconds."""
+        v = ctypes.c_double()
+        rc = lib().snlm_job_device_ms(self._ptr, ctypes.c_uint64(ticket), ctypes.byref(v))
+        if rc != OK:
+            raise SnlmError(rc, "snlm_job_device_ms")
+        return v.value
 
     def job_times(self, ticket: int):
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()

@@ -58,7 +58,6 @@ def build(jobs: int | None = None, only_s=None, verbose: bool = False, increment
     s_values = list(range(0, 17)) if only_s is None else sorted(set([0] + list(only_s)))
     objs, cmds = [], []
     dev_deps = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".hip"))]
-    dev_deps.append(os.path.join(ROOT, "include", "snlm.h"))
     for s in s_values:
         o = os.path.join(BUILD, "snlm_inst_s%d.o" % s)
         objs.append(o)

@@ -37,6 +37,31 @@ __global__ void snlm_clear_counters(uint32_t* counters, int n) {
     if (i < n) counters[i] = 0u;
 }
 
+// Served jobs: copies between the caller's images and their arena slots, one
+// launch per round.  Block row y of the grid copies image y of the table; its
+// blocks stride over the rows, its threads over the elements of a row
+// (coalesced).  Elements are esz = 2 or 4 bytes.
+struct CopyDesc {
+    const void* src;
+    void* dst;
+    int32_t rows, cols, src_ld, dst_ld, esz, pad;
+};
+
+__global__ __launch_bounds__(256) void snlm_copy_images(const CopyDesc* tab) {
+    const CopyDesc d = tab[blockIdx.y];
+    for (int r = blockIdx.x; r < d.rows; r += gridDim.x) {
+        if (d.esz == 4) {
+            const float* src = (const float*)d.src + (long)r * d.src_ld;
+            float* dst = (float*)d.dst + (long)r * d.dst_ld;
+            for (int c = threadIdx.x; c < d.cols; c += blockDim.x) dst[c] = src[c];
+        } else {
+            const uint16_t* src = (const uint16_t*)d.src + (long)r * d.src_ld;
+            uint16_t* dst = (uint16_t*)d.dst + (long)r * d.dst_ld;
+            for (int c = threadIdx.x; c < d.cols; c += blockDim.x) dst[c] = src[c];
+        }
+    }
+}
+
 // ---- SURE combination (Sec. 3.1, eqs. A and bb, Alg. 4) ----
 constexpr int kStatBlocks = 512;   // fixed grid: the FP64 sums are reproducible
 constexpr int kStatThreads = 256;
@@ -504,12 +529,24 @@ struct LaunchSlot {
     int g_ncnt = 0;
 };
 
+// A timing event recorded on the caller's stream when jobs were submitted;
+// jobs submitted together share one.
+struct SubmitMark {
+    hipEvent_t ev = nullptr;
+    int refs = 0;
+};
+
+// A served job.  Its arena region (need bytes at off) holds, in order, the
+// staged input (H x W, the job's dtype), the FP32 intermediate (H x Wp) and
+// the FP32 output (H x W), each region aligned.
 struct ServeJob {
     uint64_t ticket;
     snlm_job job;
     size_t need;
     size_t off = 0;
+    SubmitMark* mark = nullptr;      // its submit event
     double t_submit = 0, t_admit = 0, t_done = 0;
+    double dev_ms = -1.0;            // device time from its submit event to the end of its round
     int status = SNLM_PENDING;
 };
 
@@ -568,6 +605,12 @@ struct snlm_ctx {
     std::vector<LaunchSlot> serve_slots;
     std::vector<uint32_t*> serve_status;
     std::vector<uint32_t*> h_serve_status;
+    std::vector<hipEvent_t> ev_pool;     // timing events for submits (recycled at retirement)
+    int inflight = 0;                    // admitted jobs whose round has not retired
+    // per serve stream: the round's copy table (device, pinned staging)
+    std::vector<char*> d_copy, h_copy;
+    std::vector<size_t> copy_cap;
+    hipEvent_t ev_sync = nullptr;        // end of a synchronous call on the caller's stream
 };
 
 namespace {
@@ -1209,6 +1252,12 @@ void free_slot(LaunchSlot& s) {
 // ---------------------------------------------------------------- serving --
 constexpr int kServeStreams = 3;  // launches that may overlap on the device
 
+// Arena layout of a served job: staged input, FP32 intermediate, FP32 output.
+size_t serve_in_bytes(const snlm_job& j) {
+    return align_up((size_t)j.H * j.W * (j.dtype == SNLM_F16 ? 2 : 4), kAlign);
+}
+size_t serve_out_bytes(const snlm_job& j) { return align_up((size_t)j.H * j.W * 4, kAlign); }
+
 void serve_loop(snlm_ctx* c);
 
 int start_scheduler(snlm_ctx* c) {
@@ -1218,6 +1267,9 @@ int start_scheduler(snlm_ctx* c) {
     c->serve_slots.resize(kServeStreams * 4);
     c->serve_status.resize(kServeStreams, nullptr);
     c->h_serve_status.resize(kServeStreams, nullptr);
+    c->d_copy.resize(kServeStreams, nullptr);
+    c->h_copy.resize(kServeStreams, nullptr);
+    c->copy_cap.resize(kServeStreams, 0);
     for (int i = 0; i < kServeStreams; ++i) {
         HIP_CHECK(c, hipStreamCreateWithFlags(&c->serve_streams[i], hipStreamNonBlocking));
         HIP_CHECK(c, hipMalloc(&c->serve_status[i], sizeof(uint32_t)));
@@ -1230,18 +1282,62 @@ int start_scheduler(snlm_ctx* c) {
     return SNLM_OK;
 }
 
-// Launches every admitted job as one round: per kernel class, one persistent
-// launch on stream `si`, its tables in slots [4*si, 4*si+4) (more classes
-// than that wait for the next round).
-int launch_round(snlm_ctx* c, std::vector<std::shared_ptr<ServeJob>>& round, int si,
-                 InFlight& fl) {
+// Launches every admitted job as one round on serve stream si, after the
+// caller's stream has reached the newest job's submit (jobs are submitted in
+// order on that one stream, so its event covers the older ones):
+//   1. one copy launch stages every input into its arena slot;
+//   2. per kernel class, the two persistent launches compute from the staged
+//      input through the arena intermediate into the arena output slot
+//      (tables in slots [4*si, 4*si+4); more classes wait for a later round);
+//   3. one copy launch writes every output to the caller's buffer;
+//   4. the device status word and the round's completion event.
+int launch_round(snlm_ctx* c, std::vector<std::shared_ptr<ServeJob>>& round, int si, InFlight& fl) {
     hipStream_t st = c->serve_streams[si];
-    std::vector<const snlm_job*> js;
-    std::vector<char*> mids;
-    for (auto& sj : round) {
-        js.push_back(&sj->job);
-        mids.push_back(c->arena + sj->off);
+    const ServeJob* newest = round[0].get();
+    for (auto& sj : round)
+        if (sj->ticket > newest->ticket) newest = sj.get();
+    HIP_CHECK(c, hipStreamWaitEvent(st, newest->mark->ev, 0));
+    const size_t n = round.size();
+    std::vector<snlm::CopyDesc> cp(2 * n);
+    std::vector<snlm_job> staged(n);
+    std::vector<const snlm_job*> js(n);
+    std::vector<char*> mids(n);
+    int max_rows = 1;
+    for (size_t i = 0; i < n; ++i) {
+        const snlm_job& j = round[i]->job;
+        char* base = c->arena + round[i]->off;
+        char* mid = base + serve_in_bytes(j);
+        float* out = (float*)(mid + mid_bytes(j.H, j.W));
+        staged[i] = j;
+        staged[i].img = base;
+        staged[i].ld_in = j.W;
+        staged[i].out = out;
+        staged[i].ld_out = j.W;
+        js[i] = &staged[i];
+        mids[i] = mid;
+        cp[i] = {j.img, base, j.H, j.W, j.ld_in, j.W, j.dtype == SNLM_F16 ? 2 : 4, 0};
+        cp[n + i] = {out, j.out, j.H, j.W, j.W, j.ld_out, 4, 0};
+        max_rows = std::max(max_rows, j.H);
     }
+    const size_t cbytes = cp.size() * sizeof(snlm::CopyDesc);
+    if (c->copy_cap[si] < cbytes) {
+        // the stream is idle (its last round retired), so nothing reads these
+        if (c->d_copy[si]) HIP_CHECK(c, hipFree(c->d_copy[si]));
+        if (c->h_copy[si]) HIP_CHECK(c, hipHostFree(c->h_copy[si]));
+        c->d_copy[si] = c->h_copy[si] = nullptr;
+        c->copy_cap[si] = 0;
+        const size_t cap = align_up(std::max(cbytes * 2, (size_t)1 << 14), kAlign);
+        HIP_CHECK(c, hipMalloc(&c->d_copy[si], cap));
+        HIP_CHECK(c, hipHostMalloc(&c->h_copy[si], cap, hipHostMallocDefault));
+        c->copy_cap[si] = cap;
+    }
+    std::memcpy(c->h_copy[si], cp.data(), cbytes);
+    HIP_CHECK(c, hipMemcpyAsync(c->d_copy[si], c->h_copy[si], cbytes, hipMemcpyHostToDevice, st));
+    const dim3 cgrid(std::min(max_rows, 64), (unsigned)n);
+    const snlm::CopyDesc* tab_in = (const snlm::CopyDesc*)c->d_copy[si];
+    const snlm::CopyDesc* tab_out = tab_in + n;
+    void* a_in[] = {(void*)&tab_in};
+    HIP_CHECK(c, hipLaunchKernel((const void*)&snlm::snlm_copy_images, cgrid, dim3(256), a_in, 0, st));
     std::vector<ClassPlan> plans;
     plan_classes(c, js, mids, plans);
     if (plans.size() > 4) return fail(c, SNLM_EINVAL, "too many classes in one round");
@@ -1251,12 +1347,24 @@ int launch_round(snlm_ctx* c, std::vector<std::shared_ptr<ServeJob>>& round, int
         if (!rc) rc = launch_class(c, sl, st, c->serve_status[si], false);
         if (rc) return rc;
     }
+    void* a_out[] = {(void*)&tab_out};
+    HIP_CHECK(c, hipLaunchKernel((const void*)&snlm::snlm_copy_images, cgrid, dim3(256), a_out, 0, st));
     HIP_CHECK(c, hipMemcpyAsync(c->h_serve_status[si], c->serve_status[si], sizeof(uint32_t),
                                 hipMemcpyDeviceToHost, st));
-    if (!fl.done) HIP_CHECK(c, hipEventCreateWithFlags(&fl.done, hipEventDisableTiming));
+    if (!fl.done) HIP_CHECK(c, hipEventCreate(&fl.done));  // timed: device-side latency
     HIP_CHECK(c, hipEventRecord(fl.done, st));
     fl.stream = si;
     return SNLM_OK;
+}
+
+// Drops a job's reference to its submit event; the last one returns the
+// event to the pool (caller holds c->mu).
+void release_mark(snlm_ctx* c, SubmitMark*& m) {
+    if (m && --m->refs == 0) {
+        c->ev_pool.push_back(m->ev);
+        delete m;
+    }
+    m = nullptr;
 }
 
 void serve_loop(snlm_ctx* c) {
@@ -1276,9 +1384,15 @@ void serve_loop(snlm_ctx* c) {
                 const double t = now_us();
                 const bool dev_fail = (q != hipSuccess) || *c->h_serve_status[i] != 0;
                 for (auto& sj : flights[i].jobs) {
+                    float ms = -1.0f;
+                    if (!dev_fail && hipEventElapsedTime(&ms, sj->mark->ev, flights[i].done) != hipSuccess)
+                        ms = -1.0f;
+                    sj->dev_ms = ms;
+                    release_mark(c, sj->mark);
                     sj->status = dev_fail ? SNLM_EDEVICE : SNLM_OK;
                     sj->t_done = t;
                     c->alloc.release(sj->off, sj->need);
+                    --c->inflight;
                 }
                 if (dev_fail) {
                     c->last_error = "served launch failed on the device";
@@ -1290,7 +1404,6 @@ void serve_loop(snlm_ctx* c) {
             }
             // admit in arrival order while the arena has room
             const double t = now_us();
-            std::vector<std::shared_ptr<ServeJob>> admitted;
             for (int i = 0; i < kServeStreams; ++i)
                 if (!busy[i]) {
                     free_stream = i;
@@ -1309,6 +1422,7 @@ void serve_loop(snlm_ctx* c) {
                     classes[fn] = 1;
                     round.push_back(sj);
                     c->pending.pop_front();
+                    ++c->inflight;
                 }
             }
             bool any_busy = false;
@@ -1326,17 +1440,102 @@ void serve_loop(snlm_ctx* c) {
         int rc = launch_round(c, round, free_stream, fl);
         std::lock_guard<std::mutex> lk(c->mu);
         if (rc != SNLM_OK) {
+            // nothing of this round may still run: wait for what was enqueued
+            (void)hipStreamSynchronize(c->serve_streams[free_stream]);
             const double t = now_us();
             for (auto& sj : round) {
                 sj->status = rc;
                 sj->t_done = t;
+                release_mark(c, sj->mark);
                 c->alloc.release(sj->off, sj->need);
+                --c->inflight;
             }
             continue;
         }
         fl.jobs = round;
         busy[free_stream] = true;
     }
+}
+
+// Queues one served job.  shared == nullptr: the job gets a submit event of
+// its own; otherwise *shared is recorded once (on first use) and shared, the
+// caller keeping one reference of its own.
+int submit_one(snlm_ctx* c, const snlm_job* j, SubmitMark** shared, uint64_t* ticket) {
+    const char* why = check_job(j);
+    if (why) return fail(c, SNLM_EINVAL, why);
+    if (j->kernel == SNLM_BOX && j->sum != SNLM_SUM_BLOCK)
+        return fail(c, SNLM_EINVAL, "served jobs use block-restarted sums");
+    if (j->kernel == SNLM_GAUSS_IIR) return fail(c, SNLM_EINVAL, "served jobs do not take the recursive Gaussian kernel");
+    const size_t need = snlm_serving_bytes(j->H, j->W, j->dtype);
+    if (need > c->arena_bytes) return fail(c, SNLM_ENOMEM, "job can never fit the arena");
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (c->closing) return SNLM_ECLOSED;
+    if (!c->sched_started) {
+        int rc = start_scheduler(c);
+        if (rc) return rc;
+    }
+    SubmitMark* m = shared ? *shared : nullptr;
+    if (!m) {
+        m = new SubmitMark();
+        if (!c->ev_pool.empty()) {
+            m->ev = c->ev_pool.back();
+            c->ev_pool.pop_back();
+        } else {
+            hipError_t e = hipEventCreate(&m->ev);
+            if (e != hipSuccess) {
+                delete m;
+                return hip_fail(c, e, "hipEventCreate");
+            }
+        }
+        // the served kernels read img only after the caller's stream reaches this point
+        hipError_t e = hipEventRecord(m->ev, c->user);
+        if (e != hipSuccess) {
+            c->ev_pool.push_back(m->ev);
+            delete m;
+            return hip_fail(c, e, "hipEventRecord at submit");
+        }
+        m->refs = shared ? 1 : 0;  // the caller's reference to a shared mark
+        if (shared) *shared = m;
+    }
+    auto sj = std::make_shared<ServeJob>();
+    sj->mark = m;
+    ++m->refs;
+    sj->ticket = c->next_ticket++;
+    sj->job = *j;
+    sj->need = need;
+    sj->t_submit = now_us();
+    c->pending.push_back(sj);
+    c->jobs[sj->ticket] = sj;
+    *ticket = sj->ticket;
+    c->cv.notify_all();
+    return SNLM_OK;
+}
+
+// Direct calls use the arena from offset 0; they may not run while served
+// jobs hold parts of it.
+bool serving_active(snlm_ctx* c) {
+    std::lock_guard<std::mutex> lk(c->mu);
+    return !c->pending.empty() || c->inflight > 0;
+}
+
+#define CHECK_NOT_SERVING(ctx)                                                                   \
+    do {                                                                                         \
+        if (serving_active(ctx))                                                                 \
+            return fail(ctx, SNLM_EBUSY, "served jobs hold the arena; collect them (snlm_poll) first"); \
+    } while (0)
+
+// Waits for the work the calling thread has just enqueued on the caller's
+// stream and reports device-side failures of batched launches.
+int finish_sync(snlm_ctx* c) {
+    HIP_CHECK(c, hipEventRecord(c->ev_sync, c->user));
+    HIP_CHECK(c, hipEventSynchronize(c->ev_sync));
+    uint32_t st = 0;
+    HIP_CHECK(c, hipMemcpy(&st, c->d_status, sizeof(st), hipMemcpyDeviceToHost));
+    if (st) {
+        HIP_CHECK(c, hipMemset(c->d_status, 0, sizeof(uint32_t)));
+        return fail(c, SNLM_EDEVICE, "a batched launch gave up waiting for a dependency");
+    }
+    return SNLM_OK;
 }
 
 }  // namespace
@@ -1355,6 +1554,7 @@ const char* snlm_strerror(int s) {
         case SNLM_EDEVICE: return "device or HIP runtime error";
         case SNLM_ENOTICKET: return "unknown ticket";
         case SNLM_ECLOSED: return "context is closing";
+        case SNLM_EBUSY: return "served jobs hold the arena";
         default: return "unknown status";
     }
 }
@@ -1373,7 +1573,15 @@ size_t snlm_workspace_bytes(int H, int W, snlm_dtype dtype) {
     return mid_bytes(H, W);
 }
 
-size_t snlm_serving_bytes(int H, int W, snlm_dtype dtype) { return snlm_workspace_bytes(H, W, dtype); }
+size_t snlm_serving_bytes(int H, int W, snlm_dtype dtype) {
+    if (H < 1 || W < 1) return 0;
+    snlm_job j;
+    std::memset(&j, 0, sizeof(j));
+    j.H = H;
+    j.W = W;
+    j.dtype = dtype;
+    return serve_in_bytes(j) + mid_bytes(H, W) + serve_out_bytes(j);
+}
 
 int snlm_sure_layout(int H, int W, size_t* offsets) {
     if (H < 1 || W < 1 || !offsets) return SNLM_EINVAL;
@@ -1409,6 +1617,7 @@ int snlm_create(snlm_ctx** out, int device, void* stream, void* arena, size_t ar
     if (hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking) != hipSuccess) return SNLM_EDEVICE;
     if (hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess) return SNLM_EDEVICE;
     if (hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess) return SNLM_EDEVICE;
+    if (hipEventCreateWithFlags(&c->ev_sync, hipEventDisableTiming) != hipSuccess) return SNLM_EDEVICE;
     if (hipMalloc(&c->d_status, sizeof(uint32_t)) != hipSuccess) return SNLM_EDEVICE;
     if (hipMemset(c->d_status, 0, sizeof(uint32_t)) != hipSuccess) return SNLM_EDEVICE;
     if (hipDeviceSynchronize() != hipSuccess) return SNLM_EDEVICE;
@@ -1438,6 +1647,12 @@ int snlm_destroy(snlm_ctx* c) {
         if (p) (void)hipFree(p);
     for (auto p : c->h_serve_status)
         if (p) (void)hipHostFree(p);
+    for (auto p : c->d_copy)
+        if (p) (void)hipFree(p);
+    for (auto p : c->h_copy)
+        if (p) (void)hipHostFree(p);
+    for (auto& kv : c->jobs) release_mark(c, kv.second->mark);
+    for (auto ev : c->ev_pool) (void)hipEventDestroy(ev);
     for (auto* l : {&c->t_batch, &c->t_direct, &c->t_pool})
         for (auto& ev : *l) {
             (void)hipEventDestroy(ev.first);
@@ -1448,19 +1663,26 @@ int snlm_destroy(snlm_ctx* c) {
     if (c->d_iir) (void)hipFree(c->d_iir);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+    if (c->ev_sync) (void)hipEventDestroy(c->ev_sync);
     if (c->work) (void)hipStreamDestroy(c->work);
     delete c;
     return SNLM_OK;
 }
 
-int snlm_denoise_ex(snlm_ctx* c, const snlm_job* j) {
+int snlm_enqueue_ex(snlm_ctx* c, const snlm_job* j) {
     if (!c) return SNLM_EINVAL;
     const char* why = check_job(j);
     if (why) return fail(c, SNLM_EINVAL, why);
     if (mid_bytes(j->H, j->W) > c->arena_bytes)
         return fail(c, SNLM_ENOMEM, "arena smaller than snlm_workspace_bytes(H, W)");
+    CHECK_NOT_SERVING(c);
     HIP_CHECK(c, hipSetDevice(c->device));
     return enqueue_job(c, *j, c->arena, c->user);
+}
+
+int snlm_denoise_ex(snlm_ctx* c, const snlm_job* j) {
+    int rc = snlm_enqueue_ex(c, j);
+    return rc ? rc : finish_sync(c);
 }
 
 namespace {
@@ -1596,6 +1818,7 @@ int snlm_denoise_sure(snlm_ctx* c, const snlm_job* j, float sigma, double* theta
     if (why) return fail(c, SNLM_EINVAL, why);
     if (snlm_sure_workspace_bytes(j->H, j->W) > c->arena_bytes)
         return fail(c, SNLM_ENOMEM, "arena smaller than snlm_sure_workspace_bytes(H, W)");
+    CHECK_NOT_SERVING(c);
     HIP_CHECK(c, hipSetDevice(c->device));
     return sure_enqueue(c, j, sigma, nullptr, 0, theta, stats);
 }
@@ -1726,6 +1949,7 @@ int snlm_denoise3d(snlm_ctx* c, const void* img, int ld_in, snlm_dtype dtype, fl
     if (ob < ib + (size_t)in_b && ib < ob + (size_t)out_b) return fail(c, SNLM_EINVAL, "out overlaps img");
     if (snlm_workspace3d_bytes(D, H, W) > c->arena_bytes)
         return fail(c, SNLM_ENOMEM, "arena smaller than snlm_workspace3d_bytes(D, H, W)");
+    CHECK_NOT_SERVING(c);
     HIP_CHECK(c, hipSetDevice(c->device));
     init_registry();
     const int Wp = mid_pitch(W);
@@ -1783,6 +2007,7 @@ int snlm_denoise_full(snlm_ctx* c, const snlm_job* j, float sigma, double* theta
     if (why) return fail(c, SNLM_EINVAL, std::string("bilateral parameters for this sigma: ") + why);
     if (snlm_full_workspace_bytes(j->H, j->W) > c->arena_bytes)
         return fail(c, SNLM_ENOMEM, "arena smaller than snlm_full_workspace_bytes(H, W)");
+    CHECK_NOT_SERVING(c);
     HIP_CHECK(c, hipSetDevice(c->device));
     float* comb = (float*)(c->arena + snlm_sure_workspace_bytes(j->H, j->W));
     const int Wp = mid_pitch(j->W);
@@ -1828,9 +2053,10 @@ int snlm_denoise(snlm_ctx* c, const void* img, float* out, int H, int W, int S, 
     return snlm_denoise_ex(c, &j);
 }
 
-int snlm_denoise_batch(snlm_ctx* c, const snlm_job* jobs, int n) {
+int snlm_enqueue_batch(snlm_ctx* c, const snlm_job* jobs, int n) {
     if (!c) return SNLM_EINVAL;
     if (!jobs || n < 1) return fail(c, SNLM_EINVAL, "need at least one job");
+    CHECK_NOT_SERVING(c);
     // An identical batch (same jobs, same arena, same tuning) reuses the tables
     // already on the device and only replays the graphs.
     uint64_t hash = 1469598103934665603ull;
@@ -1890,6 +2116,11 @@ int snlm_denoise_batch(snlm_ctx* c, const snlm_job* jobs, int n) {
     return SNLM_OK;
 }
 
+int snlm_denoise_batch(snlm_ctx* c, const snlm_job* jobs, int n) {
+    int rc = snlm_enqueue_batch(c, jobs, n);
+    return rc ? rc : finish_sync(c);
+}
+
 int snlm_sync(snlm_ctx* c) {
     if (!c) return SNLM_EINVAL;
     HIP_CHECK(c, hipSetDevice(c->device));
@@ -1919,6 +2150,7 @@ int snlm_autotune(snlm_ctx* c, const snlm_job* probe, int* best) {
         return fail(c, SNLM_EINVAL, "only block-restarted sums are tiled");
     if (probe->kernel == SNLM_GAUSS_IIR) return fail(c, SNLM_EINVAL, "the recursive Gaussian kernel is not tuned");
     if (mid_bytes(probe->H, probe->W) > c->arena_bytes) return fail(c, SNLM_ENOMEM, "arena too small");
+    CHECK_NOT_SERVING(c);
     HIP_CHECK(c, hipSetDevice(c->device));
     hipEvent_t e0, e1;
     HIP_CHECK(c, hipEventCreate(&e0));
@@ -1970,6 +2202,7 @@ int snlm_autotune_batch(snlm_ctx* c, const snlm_job* jobs, int n, int* best) {
     static const int cand[] = {1, 2, 3, 4};  // waves per SIMD
     std::vector<snlm_job> js(jobs, jobs + n);
     hipEvent_t e0, e1;
+    CHECK_NOT_SERVING(c);
     HIP_CHECK(c, hipSetDevice(c->device));
     HIP_CHECK(c, hipEventCreate(&e0));
     HIP_CHECK(c, hipEventCreate(&e1));
@@ -1989,10 +2222,10 @@ int snlm_autotune_batch(snlm_ctx* c, const snlm_job* jobs, int n, int* best) {
         }
         float total = 0.0f;
         for (int rep = 0; rep < 4; ++rep) {
-            int rc = snlm_denoise_batch(c, js.data(), n);
+            int rc = snlm_enqueue_batch(c, js.data(), n);
             if (rc) return rc;
             HIP_CHECK(c, hipEventRecord(e0, c->user));
-            rc = snlm_denoise_batch(c, js.data(), n);
+            rc = snlm_enqueue_batch(c, js.data(), n);
             if (rc) return rc;
             HIP_CHECK(c, hipEventRecord(e1, c->user));
             HIP_CHECK(c, hipEventSynchronize(e1));
@@ -2113,30 +2346,7 @@ int snlm_timing(snlm_ctx* c, int enable, double* batch_ms, int* batch_n, double*
 }
 
 int snlm_submit(snlm_ctx* c, const snlm_job* j, uint64_t* ticket) {
-    if (!c || !ticket) return SNLM_EINVAL;
-    const char* why = check_job(j);
-    if (why) return fail(c, SNLM_EINVAL, why);
-    if (j->kernel == SNLM_BOX && j->sum != SNLM_SUM_BLOCK)
-        return fail(c, SNLM_EINVAL, "served jobs use block-restarted sums");
-    if (j->kernel == SNLM_GAUSS_IIR) return fail(c, SNLM_EINVAL, "served jobs do not take the recursive Gaussian kernel");
-    const size_t need = snlm_serving_bytes(j->H, j->W, j->dtype);
-    if (need > c->arena_bytes) return fail(c, SNLM_ENOMEM, "job can never fit the arena");
-    std::lock_guard<std::mutex> lk(c->mu);
-    if (c->closing) return SNLM_ECLOSED;
-    if (!c->sched_started) {
-        int rc = start_scheduler(c);
-        if (rc) return rc;
-    }
-    auto sj = std::make_shared<ServeJob>();
-    sj->ticket = c->next_ticket++;
-    sj->job = *j;
-    sj->need = need;
-    sj->t_submit = now_us();
-    c->pending.push_back(sj);
-    c->jobs[sj->ticket] = sj;
-    *ticket = sj->ticket;
-    c->cv.notify_all();
-    return SNLM_OK;
+    return snlm_submit_many(c, j, 1, nullptr, ticket);
 }
 
 int snlm_poll(snlm_ctx* c, uint64_t ticket) {
@@ -2148,6 +2358,40 @@ int snlm_poll(snlm_ctx* c, uint64_t ticket) {
     if (st == SNLM_PENDING) return SNLM_PENDING;
     c->jobs.erase(it);
     return st;
+}
+
+int snlm_submit_many(snlm_ctx* c, const snlm_job* jobs, int n, const double* arrival_us, uint64_t* tickets) {
+    if (!c || !jobs || !tickets || n < 0) return SNLM_EINVAL;
+    const double t0 = now_us();
+    SubmitMark* shared = nullptr;  // all at once: one event for every job
+    for (int i = 0; i < n; ++i) {
+        tickets[i] = 0;
+        if (arrival_us) {
+            const double due = t0 + arrival_us[i];
+            for (double now = now_us(); now < due; now = now_us())
+                if (due - now > 300.0) std::this_thread::sleep_for(std::chrono::microseconds(100));
+        }
+        int rc = submit_one(c, &jobs[i], arrival_us ? nullptr : &shared, &tickets[i]);
+        if (rc) {
+            std::lock_guard<std::mutex> lk(c->mu);
+            if (shared) release_mark(c, shared);  // drop the loop's own reference
+            return rc;
+        }
+    }
+    if (shared) {
+        std::lock_guard<std::mutex> lk(c->mu);
+        release_mark(c, shared);
+    }
+    return SNLM_OK;
+}
+
+int snlm_job_device_ms(snlm_ctx* c, uint64_t ticket, double* ms) {
+    if (!c || !ms) return SNLM_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->jobs.find(ticket);
+    if (it == c->jobs.end()) return SNLM_ENOTICKET;
+    *ms = it->second->dev_ms;
+    return SNLM_OK;
 }
 
 int snlm_job_times(snlm_ctx* c, uint64_t ticket, double* ts, double* ta, double* td) {

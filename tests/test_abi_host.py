@@ -20,8 +20,10 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ("snlm_create", "snlm_destroy", "snlm_denoise", "snlm_denoise_ex",
-                     "snlm_denoise_batch", "snlm_submit", "snlm_poll", "snlm_sync",
-                     "snlm_workspace_bytes", "snlm_strerror", "snlm_last_error"):
+                     "snlm_denoise_batch", "snlm_enqueue_ex", "snlm_enqueue_batch",
+                     "snlm_submit", "snlm_submit_many", "snlm_poll", "snlm_job_device_ms",
+                     "snlm_sync", "snlm_workspace_bytes", "snlm_serving_bytes",
+                     "snlm_strerror", "snlm_last_error"):
         assert required in names
 
 
@@ -42,6 +44,17 @@ def test_workspace_bytes():
     assert snlm.workspace_bytes(512, 512) == 512 * 512 * 4
     assert snlm.workspace_bytes(3, 5) == 256  # rounded to 256 bytes
     assert snlm.workspace_bytes(0, 5) == 0
+
+
+def test_serving_bytes_cover_input_intermediate_and_output():
+    L = snlm.lib()
+    # 100 x 70: FP32 input 28000 B -> 28160, intermediate 100 x 80 x 4 = 32000 -> 32000,
+    # output 28000 -> 28160
+    assert L.snlm_serving_bytes(100, 70, 0) == 28160 + 32000 + 28160
+    # FP16 input: 14000 -> 14080
+    assert L.snlm_serving_bytes(100, 70, 1) == 14080 + 32000 + 28160
+    assert L.snlm_serving_bytes(0, 70, 0) == 0
+    assert snlm.strerror(snlm.EBUSY) == "served jobs hold the arena"
 
 
 GOOD = dict(img=0x100000, out=0x900000, H=64, W=80, S=10, K=3, h=200.0)
