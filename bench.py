@@ -181,6 +181,97 @@ def write_traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_mib
     return rec
 
 
+def counters_path():
+    return os.path.join(ROOT, "profiles", "counters_batch.json")
+
+
+def write_counters(csv_paths, last=3, out_path=None):
+    """Writes profiles/counters_batch.json from rocprofv3 --pmc CSVs of
+    --profile-batch runs (any SQ counters, one group per run).  Per batched
+    launch, each counter is the mean over the last `last` dispatches (the timed
+    steps) of its sum over shader engines and XCDs.  Derived per launch:
+    issued VALU, transcendental and SALU lane-instructions per algorithmic
+    unordered pair (pixels x S per pass), the shares of wave time spent issuing
+    VALU instructions and waiting, and the issue rates over the dispatch time.
+    Returns the record."""
+    import csv
+    from collections import defaultdict
+
+    per = defaultdict(dict)  # kernel -> counter -> value
+    dur = defaultdict(list)
+    for path in csv_paths:
+        vals = defaultdict(lambda: defaultdict(float))
+        span = {}
+        for r in csv.DictReader(open(path)):
+            k = r["Kernel_Name"]
+            if "snlm_kernel" not in k:
+                continue
+            d = int(r["Dispatch_Id"])
+            vals[(k, d)][r["Counter_Name"]] += float(r["Counter_Value"])
+            if "Start_Timestamp" in r:
+                span[(k, d)] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        kern = defaultdict(list)
+        for (k, d) in vals:
+            kern[k].append(d)
+        for k, ds in kern.items():
+            ds = sorted(ds)[-last:]
+            for c in vals[(k, ds[0])]:
+                per[k][c] = sum(vals[(k, d)][c] for d in ds) / len(ds)
+            dur[k] += [span[(k, d)] for d in ds if (k, d) in span]
+    from paper_1407_2343_amd.synth import batch_workload
+    px = sum(img.size for img, _ in batch_workload(64, 128, 1024, seed=2000))
+    pairs = px * S  # unordered pairs of one pass
+    launches = {}
+    for k, c in per.items():
+        rec = {"counters": c, "pairs": pairs}
+        ns = sum(dur[k]) / len(dur[k]) if dur[k] else None
+        rec["dispatch_ns_under_counters"] = ns
+        for name, key in (("valu_per_pair", "SQ_INSTS_VALU"), ("trans_per_pair", "SQ_INSTS_VALU_TRANS_F32"),
+                          ("salu_per_pair", "SQ_INSTS_SALU"), ("lds_per_pair", "SQ_INSTS_LDS"),
+                          ("vmem_per_pair", "SQ_INSTS_VMEM")):
+            if key in c:
+                rec[name] = c[key] * 64 / pairs
+        if "SQ_WAVE_CYCLES" in c:
+            for name, key in (("valu_active_share", "SQ_ACTIVE_INST_VALU"), ("any_active_share", "SQ_ACTIVE_INST_ANY"),
+                              ("wait_inst_share", "SQ_WAIT_INST_ANY"), ("wait_any_share", "SQ_WAIT_ANY")):
+                if key in c:
+                    rec[name] = c[key] / c["SQ_WAVE_CYCLES"]
+        if ns and "SQ_INSTS_VALU" in c:
+            rec["valu_lane_T_per_s"] = c["SQ_INSTS_VALU"] * 64 / ns / 1e3
+        if ns and "SQ_INSTS_VALU_TRANS_F32" in c:
+            rec["trans_lane_T_per_s"] = c["SQ_INSTS_VALU_TRANS_F32"] * 64 / ns / 1e3
+        launches[k] = rec
+    tot = {}
+    for name in ("valu_per_pair", "trans_per_pair", "salu_per_pair"):
+        if all(name in v for v in launches.values()) and launches:
+            tot[name] = sum(v[name] for v in launches.values()) / len(launches)
+    rec = {"what": "SQ counters of the batched step (row-pass and column-pass persistent launches) of the "
+                   "64-image ragged batch, S=10 K=3 box row_col, 2 waves per SIMD",
+           "launches": launches, "step": tot, "algorithmic_valu_per_pair": PAIR_VALU,
+           "source_sha256": source_sha()}
+    with open(out_path or counters_path(), "w") as fo:
+        json.dump(rec, fo, indent=1)
+    print(json.dumps({k: round(v, 3) for k, v in tot.items()}))
+    return rec
+
+
+def counters_from_profiles():
+    """Counter-measured instructions per pair of the batched step from the
+    committed record, if it was taken on the current sources (else None)."""
+    path = counters_path()
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha256") != source_sha():
+        return None
+    out = {k: round(v, 3) for k, v in rec["step"].items()}
+    for k, v in rec["launches"].items():
+        tag = "rows" if k.rstrip(")").endswith("true>(snlm::KernelArgs") or ", true>" in k else "cols"
+        out[tag] = {n: round(v[n], 3) for n in ("valu_per_pair", "trans_per_pair", "salu_per_pair",
+                                                 "valu_active_share", "wait_inst_share") if n in v}
+    return out
+
+
 # ----------------------------------------------------------------- serving --
 def serving(torch, snlm, n_req=2000, rate_frac=0.7, seed=4000, check=32):
     """2000 requests (sizes log-uniform 64..2048 per axis, sigma U[10,40],
@@ -494,10 +585,15 @@ def main():
                     help="only the batched steps (for rocprofv3 kernel traces and counters)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only a device-to-device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--write-counters", nargs="+", metavar="CSV",
+                    help="write profiles/counters_batch.json from rocprofv3 --pmc CSVs (no GPU)")
     ap.add_argument("--write-traffic", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
                                                          "COPY_WRITE_CSV", "COPY_MIB"),
                     help="write profiles/traffic_batch.json from rocprofv3 counter CSVs (no GPU)")
     a = ap.parse_args()
+    if a.write_counters:
+        write_counters(a.write_counters)
+        return
     if a.write_traffic:
         write_traffic(*a.write_traffic[:4], int(a.write_traffic[4]))
         return
@@ -604,6 +700,7 @@ def main():
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
             "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
             "traffic": traffic_from_profiles(),
+            "counters": counters_from_profiles(),
             "kernel": "snlm_kernel<10,3,box> row + column persistent launches (one graph replay)",
             "kernel_ms": round(kernel_ms, 4),
             "alg_valu_per_pair": PAIR_VALU, "pairs_per_launch": int(pairs),
