@@ -182,6 +182,25 @@ int snlm_denoise_ex(snlm_ctx *ctx, const snlm_job *job);
  * stream. */
 int snlm_enqueue_ex(snlm_ctx *ctx, const snlm_job *job);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * two passes as snlm_enqueue_ex, enqueued on `stream` (a hipStream_t of the
+ * current device; NULL = legacy default stream), with no context and no
+ * arena.  The FP32 intermediate lives in a file-scope device array of
+ * SNLM_STATIC_SCRATCH_BYTES that each GPU the library runs on holds until the
+ * process ends; the call makes no hipMalloc, hipFree or other allocating call
+ * (the array's device address is looked up once per device, at snlm_create or
+ * at the first call).  Every call on one GPU shares that array: calls whose
+ * kernels overlap in time on one GPU (different streams, or other threads)
+ * race and give wrong results; order them.  Results are bitwise those of
+ * snlm_enqueue_ex.  Box jobs with plain or Kahan sums run one segment per line.
+ * Errors: SNLM_EINVAL (as snlm_denoise_ex, and for SNLM_GAUSS_IIR, which needs
+ * library buffers), SNLM_ENOMEM (H x Wp x 4 bytes, Wp = W rounded up to 16,
+ * above SNLM_STATIC_SCRATCH_BYTES), SNLM_EDEVICE (HIP runtime errors).  There
+ * is no context, so there is no snlm_last_error detail. */
+#define SNLM_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int snlm_enqueue_static(const snlm_job *job, void *stream);
+
 /* Many images in two persistent launches per (S, K, kernel, order) class,
  * captured once in a HIP graph (first-pass launch + second-pass launch)
  * and replayed.  The line groups of every image of a pass

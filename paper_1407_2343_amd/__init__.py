@@ -76,6 +76,7 @@ def lib():
             L.snlm_denoise_ex.argtypes = [vp, jp]
             L.snlm_denoise_batch.argtypes = [vp, jp, i]
             L.snlm_enqueue_ex.argtypes = [vp, jp]
+            L.snlm_enqueue_static.argtypes = [jp, vp]
             L.snlm_enqueue_batch.argtypes = [vp, jp, i]
             L.snlm_submit_many.argtypes = [vp, jp, i, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_uint64)]
@@ -512,6 +513,16 @@ def denoise(x, S: int, K: int, h: float, kernel: str = "box", order: str = "row_
     """Separable NLM of a 2D float32/float16 device tensor; returns float32.
     Ordered on the current stream like any PyTorch op."""
     return default_context().denoise(x, S, K, h, kernel, order, sum, beta, seg_len, out)
+
+
+def enqueue_static(job: Job, stream=None) -> int:
+    """``snlm_enqueue_static``: both passes of one job on ``stream`` (a
+    torch.cuda.Stream, or the current stream) with the intermediate in the
+    library's static device array; no context, no allocation.  Returns the
+    status code."""
+    torch = _torch()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    return lib().snlm_enqueue_static(ctypes.byref(job), ctypes.c_void_p(st.cuda_stream))
 
 
 def denoise_batch(xs, S: int, K: int, hs, kernel: str = "box", order: str = "row_col", beta=None):

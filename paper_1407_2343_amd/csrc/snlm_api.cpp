@@ -1540,6 +1540,39 @@ int finish_sync(snlm_ctx* c) {
 
 }  // namespace
 
+// ------------------------------------------------ allocation-free entry point --
+namespace snlm {
+// FP32 intermediate image of snlm_enqueue_static: a file-scope device array
+// (each GPU the library runs on holds its own copy until the process ends).
+// In host code the name is only a stand-in; kernels receive the device
+// address that hipGetSymbolAddress returns for the current device.
+constexpr size_t kStaticScratchFloats = (size_t)SNLM_STATIC_SCRATCH_BYTES / sizeof(float);
+__device__ __align__(256) float scratch[kStaticScratchFloats];
+}  // namespace snlm
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices];  // device address of snlm::scratch per device (nullptr: not looked up)
+
+// Device address of snlm::scratch on device dev, which must be current;
+// looked up once per device.
+int static_scratch(int dev, float** out) {
+    if (dev < 0 || dev >= kMaxDevices) return SNLM_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(snlm::scratch)) != hipSuccess || p == nullptr)
+            return SNLM_EDEVICE;
+        g_scratch_ptr[dev] = (float*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SNLM_OK;
+}
+
+}  // namespace
+
 // ================================================================= C ABI ===
 extern "C" {
 
@@ -1623,6 +1656,10 @@ int snlm_create(snlm_ctx** out, int device, void* stream, void* arena, size_t ar
     if (hipDeviceSynchronize() != hipSuccess) return SNLM_EDEVICE;
     c->alloc.reset(arena_bytes);
     if (const char* m = std::getenv("SNLM_BATCH_MODE")) c->batch_split = std::strcmp(m, "fused") != 0;
+    {
+        float* unused = nullptr;
+        (void)static_scratch(device, &unused);  // set-up for snlm_enqueue_static (retried there)
+    }
     *out = c.release();
     return SNLM_OK;
 }
@@ -1683,6 +1720,39 @@ int snlm_enqueue_ex(snlm_ctx* c, const snlm_job* j) {
 int snlm_denoise_ex(snlm_ctx* c, const snlm_job* j) {
     int rc = snlm_enqueue_ex(c, j);
     return rc ? rc : finish_sync(c);
+}
+
+int snlm_enqueue_static(const snlm_job* j, void* stream) {
+    if (check_job(j)) return SNLM_EINVAL;
+    if (j->kernel == SNLM_GAUSS_IIR) return SNLM_EINVAL;  // needs the library's distance buffers
+    if ((size_t)j->H * (size_t)mid_pitch(j->W) > snlm::kStaticScratchFloats) return SNLM_ENOMEM;
+    int dev = -1, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SNLM_EDEVICE;
+    float* mid = nullptr;
+    int rc = static_scratch(dev, &mid);
+    if (rc) return rc;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return SNLM_EDEVICE;
+    const hipStream_t st = (hipStream_t)stream;
+    for (int pass = 0; pass < 2; ++pass) {
+        const void* fn = kernel_fn(*j, pass);
+        if (!fn) return SNLM_EDEVICE;
+        int seg = j->seg_len;
+        if (seg <= 0) {  // the direct calls' untuned choice: one wave per SIMD
+            const bool rows = pass_rows(*j, pass);
+            const int n = rows ? j->W : j->H, nlines = rows ? j->H : j->W;
+            seg = heuristic_seg_len((nlines + snlm::kLanes - 1) / snlm::kLanes, n, 4 * std::max(ncu, 1));
+        }
+        PassDesc d;
+        fill_pass(d, *j, pass, mid, seg, false);  // whole-line sums: one segment, no scan buffer
+        KernelArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.direct = d;
+        void* args[] = {&a};
+        if (hipLaunchKernel(fn, dim3(d.ngroups * d.nseg), dim3(snlm::kLanes), args, 0, st) != hipSuccess)
+            return SNLM_EDEVICE;
+    }
+    return SNLM_OK;
 }
 
 namespace {
