@@ -241,7 +241,8 @@ constexpr int kVarIirKey = snlm::kNumVariants;
 int variant_of(const snlm_job& j) {
     if (j.kernel == SNLM_GAUSS_IIR) return kVarIirKey;
     if (j.kernel == SNLM_GAUSS) return snlm::kVarGauss;
-    return j.sum == SNLM_SUM_KAHAN ? snlm::kVarBoxKahan : snlm::kVarBox;
+    if (j.sum == SNLM_SUM_KAHAN) return snlm::kVarBoxKahan;
+    return j.sum == SNLM_SUM_PLAIN ? snlm::kVarBoxPlain : snlm::kVarBox;
 }
 
 bool pass_rows(const snlm_job& j, int pass) { return (pass == 0) == (j.order == SNLM_ROW_COL); }

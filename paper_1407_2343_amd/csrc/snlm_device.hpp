@@ -33,9 +33,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "snlm_lift.hpp"
+
 namespace snlm {
 
-constexpr int kChunk = 16;  // samples per chunk; also the block-restart period
 constexpr int kMaxS = 16;   // search half-width limit (S <= kChunk)
 constexpr int kMaxK = 8;    // patch half-width limit
 constexpr int kLanes = 64;  // lines per wave
@@ -137,6 +138,15 @@ constexpr int kVecF32 = 5;           // 16-byte loads per lane for an FP32 input
 constexpr int kVecF16 = 3;           // 16-byte loads per lane for an FP16 input tile
 constexpr int kTileIn = kLanes * kRowF32;   // floats of LDS for the input tile
 constexpr int kTileOut = kLanes * kStage;   // floats of LDS for the output tile
+// 16-byte vectors per line that hold COUNT consecutive FP32 samples starting
+// anywhere in the first vector.
+constexpr int win_vectors(int count) { return (count + 6) / 4; }
+// LDS floats of a row kernel: the chunk tiles, or the pre-chunk's sample
+// window of COUNT samples per line when that is larger.
+constexpr int row_lds_floats(int count) {
+    return kTileIn + kTileOut > kLanes * 4 * win_vectors(count) ? kTileIn + kTileOut
+                                                                 : kLanes * 4 * win_vectors(count);
+}
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
@@ -163,6 +173,7 @@ struct LineIO {
     int32_t nlines;
     int32_t lane;
     int32_t n;
+    uint32_t out_bytes;  // extent of the output buffer
     bool f16;
     bool stage_in;       // lines contiguous in the input: use the LDS tile
     bool stage_out;      // lines contiguous and 16-byte aligned in the output
@@ -170,22 +181,56 @@ struct LineIO {
     float* tile_out;     // output tile (kTileOut floats of LDS)
 
     // count samples starting at position p (reflected), into v[0..count)
+    // (the lane's line start is the per-lane offset, the position the
+    // wave-uniform one; samples inside the line need no reflection)
+    // sample at per-lane byte offset vo plus uniform byte offset so
+    __device__ __forceinline__ float load_at(int vo, int so) const {
+        if (f16) {
+            const unsigned short bits = __builtin_amdgcn_raw_buffer_load_b16(rin, vo, so, 0);
+            return (float)__builtin_bit_cast(_Float16, bits);
+        }
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rin, vo, so, 0));
+    }
     template <int COUNT>
     __device__ __forceinline__ void load(int p, float* v) const {
-        if (f16) {
+        if (p >= 0 && p + COUNT <= n) {
 #pragma unroll
-            for (int t = 0; t < COUNT; ++t) {
-                int off = in_base_b + refl(p + t, n) * in_pos_b;
-                unsigned short bits = __builtin_amdgcn_raw_buffer_load_b16(rin, off, 0, 0);
-                v[t] = (float)__builtin_bit_cast(_Float16, bits);
-            }
+            for (int t = 0; t < COUNT; ++t) v[t] = load_at(in_base_b, (p + t) * in_pos_b);
         } else {
 #pragma unroll
-            for (int t = 0; t < COUNT; ++t) {
-                int off = in_base_b + refl(p + t, n) * in_pos_b;
-                v[t] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rin, off, 0, 0));
-            }
+            for (int t = 0; t < COUNT; ++t) v[t] = load_at(in_base_b + refl(p + t, n) * in_pos_b, 0);
         }
+    }
+
+    // The pre-chunk's sample window: COUNT samples from position p into v.
+    // Rows inside the line go through LDS (the whole tile region: nothing
+    // else is in flight there at a tile's start) with 16-byte loads along
+    // each row, instead of COUNT per-lane loads that touch a cache line per
+    // lane each.
+    template <int COUNT>
+    __device__ __forceinline__ void load_window(int p, float* v) const {
+        if (!(stage_in && !f16 && p >= 0 && p + COUNT <= n)) {
+            load<COUNT>(p, v);
+            return;
+        }
+        constexpr int V = win_vectors(COUNT);
+        typedef __attribute__((address_space(3))) void* lds_ptr;
+        // load j = lane + 64 r covers line j / V, vector j % V of that line,
+        // and lands at LDS byte 16 j
+#pragma unroll
+        for (int r = 0; r < V; ++r) {
+            const int j = lane + 64 * r;
+            const int line = min(line0 + j / V, nlines - 1);
+            const int e = ((line * in_line + p) & ~3) + 4 * (j % V);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, (lds_ptr)(tile_in + 256 * r), 16, e * 4, 0, 0, 0);
+        }
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+        __syncthreads();
+        const int line = min(line0 + lane, nlines - 1);
+        const int m = (line * in_line + p) & 3;
+#pragma unroll
+        for (int t = 0; t < COUNT; ++t) v[t] = tile_in[lane * 4 * V + m + t];
+        __syncthreads();
     }
 
     // Whether the chunk of samples [p, p + kChunk) goes through the LDS tile.
@@ -251,48 +296,57 @@ struct LineIO {
     }
 
     __device__ __forceinline__ void store(int p, float v) const {
-        int off = out_base_b + p * out_pos_b;
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rout, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rout, out_base_b, p * out_pos_b, 0);
     }
 
     // Stores this lane's outputs y[0..kChunk) at positions c0.. (only those
-    // below end, and only for active lanes).
+    // below end).  Lanes past the last line repeat the last line's work, so
+    // their stores write that line's values to its addresses (the same bits)
+    // and need no lane mask.
     // stage_out requires every line start and c0 to be 4-element aligned, so
-    // the 16-byte stores below are aligned.
+    // the 16-byte stores below are aligned; tile rows past the last line go
+    // past the buffer's extent (its size as the offset), where the bounds
+    // check drops them.
     // Returns true when the chunk went out as the 4 tile stores.
-    __device__ __forceinline__ bool store_chunk(int c0, int end, bool active, const float* y) const {
-        if (stage_out && c0 + kChunk <= end) {
+    // store_full: the same for a chunk that lies wholly before end.
+    __device__ __forceinline__ bool store_full(int c0, const float* y) const {
+        if (stage_out) return store_staged(c0, y);
 #pragma unroll
-            for (int i = 0; i < kChunk; ++i) tile_out[lane * kStage + i] = y[i];
-            __syncthreads();
-            const int col = (lane & 3) * 4;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = (lane >> 2) + 16 * r;
-                u32x4 w;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) w[e] = __builtin_bit_cast(unsigned, tile_out[row * kStage + col + e]);
-                if (line0 + row < nlines) {
-                    const int off = ((line0 + row) * out_line + c0 + col) * 4;
-                    __builtin_amdgcn_raw_buffer_store_b128(w, rout, off, 0, 0);
-                }
-            }
-            __syncthreads();
-            return (line0 + 63 < nlines);  // all 4 stores issued by every lane
-        }
-        if (active) {
-#pragma unroll
-            for (int i = 0; i < kChunk; ++i)
-                if (c0 + i < end) store(c0 + i, y[i]);
-        }
+        for (int i = 0; i < kChunk; ++i) store(c0 + i, y[i]);
         return false;
+    }
+    __device__ __forceinline__ bool store_chunk(int c0, int end, const float* y) const {
+        if (c0 + kChunk <= end) return store_full(c0, y);
+#pragma unroll
+        for (int i = 0; i < kChunk; ++i)
+            if (c0 + i < end) store(c0 + i, y[i]);
+        return false;
+    }
+    __device__ __forceinline__ bool store_staged(int c0, const float* y) const {
+#pragma unroll
+        for (int i = 0; i < kChunk; ++i) tile_out[lane * kStage + i] = y[i];
+        __syncthreads();
+        const int col = (lane & 3) * 4;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = (lane >> 2) + 16 * r;
+            u32x4 w;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) w[e] = __builtin_bit_cast(unsigned, tile_out[row * kStage + col + e]);
+            const int off = line0 + row < nlines ? ((line0 + row) * out_line + c0 + col) * 4 : (int)out_bytes;
+            __builtin_amdgcn_raw_buffer_store_b128(w, rout, off, 0, 0);
+        }
+        __syncthreads();
+        return true;
     }
 };
 
 // Filters samples [seg_a, seg_b) of one line.  seg_a is a multiple of kChunk.
-template <int S, int K, bool GAUSS, bool KAHAN>
-__device__ __forceinline__ void run_segment(const PassDesc& d, const LineIO& io, bool active,
-                                            int seg_a, int seg_b) {
+// RESTART (box only): the running sums restart at the block positions (the
+// default, "block"); otherwise they run over the whole segment ("plain", or
+// "kahan" with KAHAN), starting from d.carry where a scan provided states.
+template <int S, int K, bool GAUSS, bool KAHAN, bool RESTART>
+__device__ __forceinline__ void run_segment(const PassDesc& d, const LineIO& io, int seg_a, int seg_b) {
     constexpr int C = kChunk;
     constexpr int NX = C + S + 2 * K + 1;  // x window: positions c0-K-1 .. c0+C+S+K-1
     constexpr int NP = C + S;              // accumulators: centres c0 .. c0+C+S-1
@@ -300,13 +354,13 @@ __device__ __forceinline__ void run_segment(const PassDesc& d, const LineIO& io,
     constexpr int R0 = (C - S) % C;        // restart offset within a chunk
     constexpr int XO = K + 1;              // x index of centre c0
     static_assert(S >= 1 && S <= kMaxS && K >= 0 && K <= kMaxK, "parameter range");
+    static_assert(!(GAUSS && (KAHAN || RESTART)) && !(KAHAN && RESTART), "variant");
 
     // Everything runs on the scaled samples xs = a x: the lift then needs no
     // multiply, and the average of scaled samples is unscaled once per output
     // (y = (P / Q) / a).
     const float alpha = d.alpha;
     const float inv_alpha = d.inv_alpha;
-    const bool restart = d.restart != 0;
     float xs[NX], P[NP], Q[NP], nx[C];  // nx: the next chunk's samples
     float R[S];
     float Rc[KAHAN ? S : 1];
@@ -316,8 +370,18 @@ __device__ __forceinline__ void run_segment(const PassDesc& d, const LineIO& io,
     for (int k = 0; k <= K; ++k) g[k] = d.taps[k];
 
     // ---- window for the pre-chunk at c0 = seg_a - C ----
+    // Column passes: the first chunk's loads go out first; the pre-chunk
+    // waits for the window's, so the loop finds them complete and its own
+    // wait at the top counts only the previous iteration's loads.  Row
+    // passes: the window goes through the LDS tile region first.
     int c0 = seg_a - C;
-    io.template load<NX>(c0 - K - 1, xs);
+    if (io.stage_in) {
+        io.template load_window<NX>(c0 - K - 1, xs);
+        io.issue_chunk(seg_a + S + K, nx);
+    } else {
+        io.issue_chunk(seg_a + S + K, nx);
+        io.template load<NX>(c0 - K - 1, xs);
+    }
 #pragma unroll
     for (int j = 0; j < NX; ++j) xs[j] = alpha * xs[j];
 #pragma unroll
@@ -325,81 +389,39 @@ __device__ __forceinline__ void run_segment(const PassDesc& d, const LineIO& io,
         P[i] = xs[i + XO];
         Q[i] = 1.0f;
     }
-    io.issue_chunk(seg_a + S + K, nx);
-
-    // Lifted diagonal D_s(v) for v = c0-K+m, m in [m0, ND) (Gaussian).
-    auto lift_diag = [&](int s, int m0) {
-#pragma unroll
-        for (int m = 0; m < ND; ++m) {
-            if (m < m0) continue;
-            float dd = xs[m + 1] - xs[m + 1 + s];
-            Dv[m] = dd * dd;
-        }
-    };
-    // Gaussian FIR of the lifted diagonal at centre index i.
-    auto gauss_d2 = [&](int i) -> float {
-        float r = Dv[i + K];
-#pragma unroll
-        for (int k = 1; k <= K; ++k) r = __builtin_fmaf(g[k], Dv[i + K - k] + Dv[i + K + k], r);
-        return r;
-    };
-    // Direct window sum of the lifted diagonal at centre index i (box).
-    auto box_init = [&](int i, int s) -> float {
-        float r = 0.0f;
-#pragma unroll
-        for (int k = -K; k <= K; ++k) {
-            float dd = xs[i + XO + k] - xs[i + XO + k + s];
-            r = (k == -K) ? dd * dd : __builtin_fmaf(dd, dd, r);
-        }
-        return r;
-    };
-    // One step of the recursion of eq. recursion at centre index i.
-    auto box_slide = [&](int i, int s, int si) {
-        float de = xs[i + 2 * K + 1] - xs[i + 2 * K + 1 + s];  // enters: D_s(u+K)
-        float dl = xs[i] - xs[i + s];                          // leaves: D_s(u-K-1)
-        if constexpr (KAHAN) {
-            float t = __builtin_fmaf(de, de, -(dl * dl));
-            float y = t - Rc[si];
-            float sum = R[si] + y;
-            Rc[si] = (sum - R[si]) - y;
-            R[si] = sum;
-        } else {
-            R[si] = __builtin_fmaf(-dl, dl, __builtin_fmaf(de, de, R[si]));
-        }
-    };
 
     // ---- pre-chunk: pairs (u, u+s) with u in [seg_a - s, seg_a) ----
 #pragma unroll
     for (int s = 1; s <= S; ++s) {
         const int si = s - 1;
-        if constexpr (GAUSS) lift_diag(s, C - s);
+        if constexpr (GAUSS) lift_diag(xs, Dv, s, C - s);
 #pragma unroll
         for (int i = R0; i < C; ++i) {
             float r;
             if constexpr (GAUSS) {
                 if (i < C - s) continue;
-                r = gauss_d2(i);
+                r = gauss_d2<K>(Dv, g, i);
             } else {
                 if (i == R0) {
-                    if (d.carry != nullptr && seg_a > 0) {
+                    if (!RESTART && d.carry != nullptr && seg_a > 0) {
                         // the whole-line recursion's state here (snlm_carry_kernel)
                         const int line = min(io.line0 + io.lane, io.nlines - 1);
                         const long at = ((long)(seg_a / d.seg_len - 1) * S + si) * io.nlines + line;
                         R[si] = d.carry[at];
                         if constexpr (KAHAN) Rc[si] = d.carry[at + (long)(d.nseg - 1) * S * io.nlines];
                     } else {
-                        R[si] = box_init(i, s);
+                        R[si] = box_init<K, XO>(xs, i, s);
                         if constexpr (KAHAN) Rc[si] = 0.0f;
                     }
+                } else if constexpr (KAHAN) {
+                    box_slide_kahan<K>(xs, R[si], Rc[si], i, s);
                 } else {
-                    box_slide(i, s, si);
+                    box_slide<K>(xs, R[si], i, s);
                 }
                 if (i < C - s) continue;
                 r = R[si];
             }
-            float w = __builtin_amdgcn_exp2f(-__builtin_fabsf(r));
-            P[i + s] = __builtin_fmaf(w, xs[i + XO], P[i + s]);
-            Q[i + s] += w;
+            accumulate_pair<XO>(xs, P, Q, i, s, pair_weight(r), false);
         }
     }
 
@@ -407,75 +429,64 @@ __device__ __forceinline__ void run_segment(const PassDesc& d, const LineIO& io,
     bool staged_store_last = false;  // the previous chunk ended with 4 tile stores
     for (c0 = seg_a;; c0 += C) {
         io.finish_chunk(c0 + S + K, nx, staged_store_last);
-        // shift the window by one chunk
-#pragma unroll
-        for (int j = 0; j < NX - C; ++j) xs[j] = xs[j + C];
-#pragma unroll
-        for (int t = 0; t < C; ++t) xs[NX - C + t] = alpha * nx[t];
-#pragma unroll
-        for (int i = 0; i < S; ++i) {
-            P[i] = P[i + C];
-            Q[i] = Q[i + C];
-        }
-#pragma unroll
-        for (int i = S; i < NP; ++i) {
-            P[i] = xs[i + XO];
-            Q[i] = 1.0f;
-        }
+        advance_chunk<S, XO>(xs, P, Q, nx, alpha);
         const bool has_next = c0 + C < seg_b;
-        if (has_next) io.issue_chunk(c0 + C + S + K, nx);
+        // Column passes fetch the next chunk unconditionally (a chunk past the
+        // segment is read and dropped), so that every iteration issues the same
+        // loads and stores and the loop waits only for the loads; row passes
+        // fill the LDS tile, which nothing may still be writing at a tile's end.
+        if (has_next || !io.stage_in) io.issue_chunk(c0 + C + S + K, nx);
 
 #pragma unroll
         for (int s = 1; s <= S; ++s) {
             const int si = s - 1;
-            // Keep the scheduler from interleaving offsets: one diagonal at a
-            // time bounds the live registers (and so raises occupancy).
-            __builtin_amdgcn_sched_barrier(0);
-            if constexpr (GAUSS) lift_diag(s, 0);
+            // Let the scheduler interleave two offsets at a time (two
+            // independent running-sum chains), but not more: that bounds the
+            // live registers (and so raises occupancy).
+            if (s % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+            if constexpr (GAUSS) lift_diag(xs, Dv, s, 0);
 #pragma unroll
             for (int i = 0; i < C; ++i) {
                 float r;
                 if constexpr (GAUSS) {
-                    r = gauss_d2(i);
+                    r = gauss_d2<K>(Dv, g, i);
                 } else {
-                    box_slide(i, s, si);
-                    if (i == R0) {
-                        // block restart: a select on a wave-uniform flag keeps
-                        // the chunk one straight-line block
-                        const float fresh = box_init(i, s);
-                        R[si] = restart ? fresh : R[si];
-                        if constexpr (KAHAN) Rc[si] = restart ? 0.0f : Rc[si];
-                    }
+                    if (RESTART && i == R0)
+                        R[si] = box_init<K, XO>(xs, i, s);  // block restart
+                    else if constexpr (KAHAN)
+                        box_slide_kahan<K>(xs, R[si], Rc[si], i, s);
+                    else
+                        box_slide<K>(xs, R[si], i, s);
                     r = R[si];
                 }
-                float w = __builtin_amdgcn_exp2f(-__builtin_fabsf(r));
-                P[i] = __builtin_fmaf(w, xs[i + XO + s], P[i]);
-                Q[i] += w;
-                P[i + s] = __builtin_fmaf(w, xs[i + XO], P[i + s]);
-                Q[i + s] += w;
+                accumulate_pair<XO>(xs, P, Q, i, s, pair_weight(r), true);
             }
         }
 
         float y[C];
-#pragma unroll
-        for (int i = 0; i < C; ++i) y[i] = (P[i] * __builtin_amdgcn_rcpf(Q[i])) * inv_alpha;
+        normalise(P, Q, inv_alpha, y);
         // Materialise all outputs before the (partly masked) stores, so that
         // the compiler does not sink the last accumulations into the store
         // branches and split the chunk into small blocks.
 #pragma unroll
         for (int i = 0; i < C; i += 4)
             asm volatile("" ::"v"(y[i]), "v"(y[i + 1]), "v"(y[i + 2]), "v"(y[i + 3]));
-        staged_store_last = io.store_chunk(c0, seg_b, active, y);
-        if (!has_next) break;
+        if (!has_next) {
+            io.store_chunk(c0, seg_b, y);
+            break;
+        }
+        // (the loop continues only after a whole chunk's stores, so every
+        // iteration issues the same memory operations)
+        staged_store_last = io.store_full(c0, y);
     }
 }
 
 // Copy / convert pass for S = 0 (the 1D NLM is then the identity).
-__device__ __forceinline__ void run_copy(const LineIO& io, bool active, int seg_a, int seg_b) {
+__device__ __forceinline__ void run_copy(const LineIO& io, int seg_a, int seg_b) {
     for (int p = seg_a; p < seg_b; ++p) {
         float v[1];
         io.template load<1>(p, v);
-        if (active) io.store(p, v[0]);
+        io.store(p, v[0]);
     }
 }
 
@@ -505,6 +516,7 @@ __device__ __forceinline__ LineIO make_io(const PassDesc& d, int line0, int lane
     io.nlines = d.nlines;
     io.lane = lane;
     io.n = d.n;
+    io.out_bytes = d.out_bytes;
     io.f16 = d.in_f16 != 0;
     io.stage_in = ROWS && d.split == 0 && d.in_pos == 1 && ((uintptr_t)d.in & 15) == 0;
     io.stage_out = ROWS && d.split == 0 && d.out_pos == 1 && (d.out_line & 3) == 0 &&
@@ -514,47 +526,48 @@ __device__ __forceinline__ LineIO make_io(const PassDesc& d, int line0, int lane
     return io;
 }
 
-template <int S, int K, bool GAUSS, bool KAHAN, bool ROWS>
+template <int S, int K, bool GAUSS, bool KAHAN, bool RESTART, bool ROWS>
 __device__ __forceinline__ void run_tile(const PassDesc& d, int group, int a, int b, float* tiles) {
     const int lane = threadIdx.x & (kLanes - 1);
     const int line0 = group * kLanes;
-    const bool active = line0 + lane < d.nlines;
     const LineIO io = make_io<ROWS>(d, line0, lane, tiles);
     if constexpr (S == 0) {
-        run_copy(io, active, a, b);
+        run_copy(io, a, b);
     } else {
-        run_segment<S, K, GAUSS, KAHAN>(d, io, active, a, b);
+        run_segment<S, K, GAUSS, KAHAN, RESTART>(d, io, a, b);
     }
 }
 
-// Loads a table entry the whole wave agrees on and keeps it in scalar
-// registers (the compiler cannot prove on its own that a value loaded through
-// a wave-uniform index is uniform).
+// Loads a table entry the whole wave agrees on (a batch's header, tiles and
+// pass descriptors, which no kernel writes) with scalar loads: read through
+// the constant address space, a wave-uniform address becomes s_load
+// instructions into scalar registers instead of per-lane loads.
 template <typename T>
 __device__ __forceinline__ T load_uniform(const T* src) {
     static_assert(sizeof(T) % 4 == 0, "word-sized");
+    typedef __attribute__((address_space(4))) const uint32_t* const_words;
+    const_words w = (const_words)(src);
     T v;
-    const uint32_t* w = reinterpret_cast<const uint32_t*>(src);
     uint32_t* o = reinterpret_cast<uint32_t*>(&v);
 #pragma unroll
-    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) o[i] = __builtin_amdgcn_readfirstlane(w[i]);
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) o[i] = w[i];
     return v;
 }
 
-// One kernel per (S, K, kernel, compensation, row/column variant).
+// One kernel per (S, K, kernel, running-sum variant, row/column variant).
 // Workgroup = one wave.
-template <int S, int K, bool GAUSS, bool KAHAN, bool ROWS>
+template <int S, int K, bool GAUSS, bool KAHAN, bool RESTART, bool ROWS>
 __global__ __launch_bounds__(kLanes) void snlm_kernel(KernelArgs args) {
     const bool batch = args.hdr != nullptr;
     BatchHeader hdr = {0, 0, 0, 0u};
     if (batch) hdr = load_uniform(args.hdr);
     __shared__ uint32_t claimed;
-    __shared__ __attribute__((aligned(16))) float tiles[ROWS ? kTileIn + kTileOut : 1];
+    __shared__ __attribute__((aligned(16))) float tiles[ROWS ? row_lds_floats(kChunk + S + 2 * K + 1) : 1];
     const bool stat = batch && args.worker_first != nullptr;
     uint32_t t_next = 0, t_end = 0;
     if (stat) {
-        t_next = __builtin_amdgcn_readfirstlane(args.worker_first[blockIdx.x]);
-        t_end = __builtin_amdgcn_readfirstlane(args.worker_first[blockIdx.x + 1]);
+        t_next = load_uniform(&args.worker_first[blockIdx.x]);
+        t_end = load_uniform(&args.worker_first[blockIdx.x + 1]);
     }
     for (int iter = 0;; ++iter) {
         PassDesc d;
@@ -607,7 +620,7 @@ __global__ __launch_bounds__(kLanes) void snlm_kernel(KernelArgs args) {
             }
             d = load_uniform(&args.jobs[job].pass[pass]);
         }
-        run_tile<S, K, GAUSS, KAHAN, ROWS>(d, group, a, b, tiles);
+        run_tile<S, K, GAUSS, KAHAN, RESTART, ROWS>(d, group, a, b, tiles);
         if (batch && pass == 0 && args.wait) {
             // publish this tile's intermediate rows (one release per tile)
             __syncthreads();

@@ -333,7 +333,7 @@ __global__ __launch_bounds__(4 * kLanes) void snlm_iir_transpose_kernel(IirTrans
 // positions c0 .. c0 + C + S - 1, and pair (u, u+s) takes d = dist(s, u).
 template <int S>
 __device__ __forceinline__ void run_segment_dist(const PassDesc& d, const LineIO& io, const DistIO& dio,
-                                                 bool active, int seg_a, int seg_b) {
+                                                 int seg_a, int seg_b) {
     constexpr int C = kChunk;
     constexpr int NX = C + S;
     constexpr int NP = C + S;
@@ -362,11 +362,8 @@ __device__ __forceinline__ void run_segment_dist(const PassDesc& d, const LineIO
 #pragma unroll
         for (int i = C - s; i < C; ++i) r[i] = dio.load(s, c0 + i);
 #pragma unroll
-        for (int i = C - s; i < C; ++i) {
-            const float w = __builtin_amdgcn_exp2f(-r[i]);
-            P[i + s] = __builtin_fmaf(w, xs[i], P[i + s]);
-            Q[i + s] += w;
-        }
+        for (int i = C - s; i < C; ++i)
+            accumulate_pair<0>(xs, P, Q, i, s, __builtin_amdgcn_exp2f(-r[i]), false);
     }
 
     // distances of offset s for the chunk at c: positions past the line's end
@@ -380,20 +377,7 @@ __device__ __forceinline__ void run_segment_dist(const PassDesc& d, const LineIO
     bool staged_store_last = false;  // the previous chunk ended with 4 tile stores
     for (c0 = seg_a;; c0 += C) {
         io.finish_chunk(c0 + S, nx, staged_store_last);
-#pragma unroll
-        for (int j = 0; j < NX - C; ++j) xs[j] = xs[j + C];
-#pragma unroll
-        for (int t = 0; t < C; ++t) xs[NX - C + t] = alpha * nx[t];
-#pragma unroll
-        for (int i = 0; i < S; ++i) {
-            P[i] = P[i + C];
-            Q[i] = Q[i + C];
-        }
-#pragma unroll
-        for (int i = S; i < NP; ++i) {
-            P[i] = xs[i];
-            Q[i] = 1.0f;
-        }
+        advance_chunk<S, 0>(xs, P, Q, nx, alpha);
         const bool has_next = c0 + C < seg_b;
         if (has_next) io.issue_chunk(c0 + C + S, nx);
 #pragma unroll
@@ -406,14 +390,10 @@ __device__ __forceinline__ void run_segment_dist(const PassDesc& d, const LineIO
                 row(s + 1, c0, rn);
             else if (has_next)
                 row(1, c0 + C, rn);
+            // (the distance as stored: a recursive-filter value can be
+            // slightly negative, and is not clamped)
 #pragma unroll
-            for (int i = 0; i < C; ++i) {
-                const float w = __builtin_amdgcn_exp2f(-rc[i]);
-                P[i] = __builtin_fmaf(w, xs[i + s], P[i]);
-                Q[i] += w;
-                P[i + s] = __builtin_fmaf(w, xs[i], P[i + s]);
-                Q[i + s] += w;
-            }
+            for (int i = 0; i < C; ++i) accumulate_pair<0>(xs, P, Q, i, s, __builtin_amdgcn_exp2f(-rc[i]), true);
             if (s < S || has_next) {
 #pragma unroll
                 for (int i = 0; i < C; ++i) rc[i] = rn[i];
@@ -427,9 +407,8 @@ __device__ __forceinline__ void run_segment_dist(const PassDesc& d, const LineIO
                              "v"(Q[i + 2]), "v"(Q[i + 3]));
         }
         float y[C];
-#pragma unroll
-        for (int i = 0; i < C; ++i) y[i] = (P[i] * __builtin_amdgcn_rcpf(Q[i])) * inv_alpha;
-        staged_store_last = io.store_chunk(c0, seg_b, active, y);
+        normalise(P, Q, inv_alpha, y);
+        staged_store_last = io.store_chunk(c0, seg_b, y);
         if (!has_next) break;
     }
 }
@@ -449,11 +428,10 @@ __global__ __launch_bounds__(kLanes) void snlm_iir_nlm_kernel(IirNlmArgs a) {
     const int seg_b = min(seg_a + d.seg_len, d.n);
     const int lane = threadIdx.x & (kLanes - 1);
     const int line0 = group * kLanes;
-    const bool active = line0 + lane < d.nlines;
     const LineIO io = make_io<ROWS>(d, line0, lane, tiles);
     const int line = min(line0 + lane, d.nlines - 1);
     const DistIO dio = make_dist_io(a.dist, a.dist_bytes, line, d.nlines, a.nv, S);
-    run_segment_dist<S>(d, io, dio, active, seg_a, seg_b);
+    run_segment_dist<S>(d, io, dio, seg_a, seg_b);
 }
 
 }  // namespace snlm

@@ -12,19 +12,22 @@ namespace {
 template <int K>
 void register_k(KernelRegistry* reg) {
     if constexpr (SNLM_S == 0) {
-        const void* f = (const void*)&snlm_kernel<0, 0, false, false, false>;
+        const void* f = (const void*)&snlm_kernel<0, 0, false, false, false, false>;
         for (int v = 0; v < kNumVariants; ++v)
             for (int r = 0; r < 2; ++r) reg->fn[0][K][v][r] = f;
         reg->div[0][K][0] = reg->div[0][K][1] = (const void*)&snlm_div_kernel<0, 0, false>;
     } else {
+        // snlm_kernel<S, K, GAUSS, KAHAN, RESTART, ROWS>
         reg->div[SNLM_S][K][0] = (const void*)&snlm_div_kernel<SNLM_S, K, false>;
         reg->div[SNLM_S][K][1] = (const void*)&snlm_div_kernel<SNLM_S, K, true>;
-        reg->fn[SNLM_S][K][kVarBox][0] = (const void*)&snlm_kernel<SNLM_S, K, false, false, false>;
-        reg->fn[SNLM_S][K][kVarBox][1] = (const void*)&snlm_kernel<SNLM_S, K, false, false, true>;
-        reg->fn[SNLM_S][K][kVarBoxKahan][0] = (const void*)&snlm_kernel<SNLM_S, K, false, true, false>;
-        reg->fn[SNLM_S][K][kVarBoxKahan][1] = (const void*)&snlm_kernel<SNLM_S, K, false, true, true>;
-        reg->fn[SNLM_S][K][kVarGauss][0] = (const void*)&snlm_kernel<SNLM_S, K, true, false, false>;
-        reg->fn[SNLM_S][K][kVarGauss][1] = (const void*)&snlm_kernel<SNLM_S, K, true, false, true>;
+        reg->fn[SNLM_S][K][kVarBox][0] = (const void*)&snlm_kernel<SNLM_S, K, false, false, true, false>;
+        reg->fn[SNLM_S][K][kVarBox][1] = (const void*)&snlm_kernel<SNLM_S, K, false, false, true, true>;
+        reg->fn[SNLM_S][K][kVarBoxKahan][0] = (const void*)&snlm_kernel<SNLM_S, K, false, true, false, false>;
+        reg->fn[SNLM_S][K][kVarBoxKahan][1] = (const void*)&snlm_kernel<SNLM_S, K, false, true, false, true>;
+        reg->fn[SNLM_S][K][kVarGauss][0] = (const void*)&snlm_kernel<SNLM_S, K, true, false, false, false>;
+        reg->fn[SNLM_S][K][kVarGauss][1] = (const void*)&snlm_kernel<SNLM_S, K, true, false, false, true>;
+        reg->fn[SNLM_S][K][kVarBoxPlain][0] = (const void*)&snlm_kernel<SNLM_S, K, false, false, false, false>;
+        reg->fn[SNLM_S][K][kVarBoxPlain][1] = (const void*)&snlm_kernel<SNLM_S, K, false, false, false, true>;
     }
     if constexpr (K < kMaxK) register_k<K + 1>(reg);
 }

@@ -9,7 +9,10 @@
 
 namespace snlm {
 
-enum Variant { kVarBox = 0, kVarBoxKahan = 1, kVarGauss = 2, kNumVariants = 3 };
+// Running-sum / patch-kernel variants of the line kernels: box with block
+// restarts (the default), box with Kahan-compensated whole-line sums, the
+// exact Gaussian FIR, box with plain whole-line sums.
+enum Variant { kVarBox = 0, kVarBoxKahan = 1, kVarGauss = 2, kVarBoxPlain = 3, kNumVariants = 4 };
 
 // fn[S][K][variant][rows]: rows = 1 is the variant for passes whose lines are
 // contiguous in memory (LDS transpose tiles), rows = 0 for column passes.

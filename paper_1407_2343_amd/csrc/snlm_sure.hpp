@@ -64,7 +64,6 @@ __device__ __forceinline__ void run_segment_div(const PassDesc& d, const LineIO&
 
     const float alpha = d.alpha;
     const float inv_alpha = d.inv_alpha;
-    const bool restart = d.restart != 0;
     float xs[NX], P[NP], Q[NP], M[NP], U1[NU], U2[NU], nx[C];
     float R[S];
     float Dv[GAUSS ? ND : 1];
@@ -89,48 +88,15 @@ __device__ __forceinline__ void run_segment_div(const PassDesc& d, const LineIO&
     }
     io.issue_chunk(seg_a + S + K, nx);
 
-    auto lift_diag = [&](int s, int m0) {
-#pragma unroll
-        for (int m = 0; m < ND; ++m) {
-            if (m < m0) continue;
-            float dd = xs[m + 1] - xs[m + 1 + s];
-            Dv[m] = dd * dd;
-        }
-    };
-    auto gauss_d2 = [&](int i) -> float {
-        float r = Dv[i + K];
-#pragma unroll
-        for (int k = 1; k <= K; ++k) r = __builtin_fmaf(g[k], Dv[i + K - k] + Dv[i + K + k], r);
-        return r;
-    };
-    auto box_init = [&](int i, int s) -> float {
-        float r = 0.0f;
-#pragma unroll
-        for (int k = -K; k <= K; ++k) {
-            float dd = xs[i + XO + k] - xs[i + XO + k + s];
-            r = (k == -K) ? dd * dd : __builtin_fmaf(dd, dd, r);
-        }
-        return r;
-    };
-    auto box_slide = [&](int i, int s, int si) {
-        float de = xs[i + 2 * K + 1] - xs[i + 2 * K + 1 + s];
-        float dl = xs[i] - xs[i + s];
-        R[si] = __builtin_fmaf(-dl, dl, __builtin_fmaf(de, de, R[si]));
-    };
     // Pair (i, i+s) of weight w: its partner terms for centre i+s, and, when
     // centre_i, its terms for centre i.
     auto pair = [&](int i, int s, float w, bool centre_i) {
+        accumulate_pair<XO>(xs, P, Q, i, s, w, centre_i);  // y: as the plain pass
         const float xi = xs[i + XO];
         const float xj = xs[i + s + XO];
         const float dc = xi - xj;  // x(i) - x(i+s)
         const float wd2 = w * (dc * dc);
-        if (centre_i) {
-            P[i] = __builtin_fmaf(w, xj, P[i]);
-            Q[i] += w;
-            M[i] += wd2;
-        }
-        P[i + s] = __builtin_fmaf(w, xi, P[i + s]);
-        Q[i + s] += w;
+        if (centre_i) M[i] += wd2;
         M[i + s] += wd2;
         if (s <= KU) {
             const float wg = GAUSS ? w * g[s] : w;
@@ -149,43 +115,32 @@ __device__ __forceinline__ void run_segment_div(const PassDesc& d, const LineIO&
 #pragma unroll
     for (int s = 1; s <= S; ++s) {
         const int si = s - 1;
-        if constexpr (GAUSS) lift_diag(s, C - s);
+        if constexpr (GAUSS) lift_diag(xs, Dv, s, C - s);
 #pragma unroll
         for (int i = R0; i < C; ++i) {
             float r;
             if constexpr (GAUSS) {
                 if (i < C - s) continue;
-                r = gauss_d2(i);
+                r = gauss_d2<K>(Dv, g, i);
             } else {
                 if (i == R0)
-                    R[si] = box_init(i, s);
+                    R[si] = box_init<K, XO>(xs, i, s);
                 else
-                    box_slide(i, s, si);
+                    box_slide<K>(xs, R[si], i, s);
                 if (i < C - s) continue;
                 r = R[si];
             }
-            pair(i, s, __builtin_amdgcn_exp2f(-__builtin_fabsf(r)), false);
+            pair(i, s, pair_weight(r), false);
         }
     }
 
     // ---- main chunks ----
     for (c0 = seg_a;; c0 += C) {
+        advance_chunk<S, XO>(xs, P, Q, nx, alpha);
 #pragma unroll
-        for (int j = 0; j < NX - C; ++j) xs[j] = xs[j + C];
+        for (int i = 0; i < S; ++i) M[i] = M[i + C];
 #pragma unroll
-        for (int t = 0; t < C; ++t) xs[NX - C + t] = alpha * nx[t];
-#pragma unroll
-        for (int i = 0; i < S; ++i) {
-            P[i] = P[i + C];
-            Q[i] = Q[i + C];
-            M[i] = M[i + C];
-        }
-#pragma unroll
-        for (int i = S; i < NP; ++i) {
-            P[i] = xs[i + XO];
-            Q[i] = 1.0f;
-            M[i] = 0.0f;
-        }
+        for (int i = S; i < NP; ++i) M[i] = 0.0f;
 #pragma unroll
         for (int i = 0; i < KU; ++i) {
             U1[i] = U1[i + C];
@@ -205,21 +160,20 @@ __device__ __forceinline__ void run_segment_div(const PassDesc& d, const LineIO&
 #pragma unroll
         for (int s = 1; s <= S; ++s) {
             const int si = s - 1;
-            if constexpr (GAUSS) lift_diag(s, 0);
+            if constexpr (GAUSS) lift_diag(xs, Dv, s, 0);
 #pragma unroll
             for (int i = 0; i < C; ++i) {
                 float r;
                 if constexpr (GAUSS) {
-                    r = gauss_d2(i);
+                    r = gauss_d2<K>(Dv, g, i);
                 } else {
-                    box_slide(i, s, si);
-                    if (i == R0) {
-                        const float fresh = box_init(i, s);
-                        R[si] = restart ? fresh : R[si];
-                    }
+                    if (i == R0)
+                        R[si] = box_init<K, XO>(xs, i, s);  // block restart
+                    else
+                        box_slide<K>(xs, R[si], i, s);
                     r = R[si];
                 }
-                pair(i, s, __builtin_amdgcn_exp2f(-__builtin_fabsf(r)), true);
+                pair(i, s, pair_weight(r), true);
             }
         }
 
@@ -234,7 +188,7 @@ __device__ __forceinline__ void run_segment_div(const PassDesc& d, const LineIO&
             const float t = __builtin_fmaf(-dx, U2[i], U1[i]);
             dd[i] = dv[i] * (__builtin_fmaf(kTwoLn2, t + spread, 1.0f) * rq);
         }
-        io.store_chunk(c0, seg_b, active, y);
+        io.store_chunk(c0, seg_b, y);
         if (active) {
 #pragma unroll
             for (int i = 0; i < C; ++i)
