@@ -334,7 +334,10 @@ def serving(torch, snlm, n_req=2000, rate_frac=0.7, seed=4000, check=32):
         return np.array(host), np.array(dev), (last - first) / 1e6, t_sub
 
     run(None, snlm.job_array(job_list[:64]))  # warm every kernel class once
+    r0, j0, us0 = srv.serving_stats()
     _, dev_sat, span_sat, sub_sat = run(None, jobs)
+    r1, j1, us1 = srv.serving_stats()
+    sat_rounds, sat_jobs, sat_host_us = r1 - r0, j1 - j0, us1 - us0
     sat_rate = n_req / span_sat
     rate = rate_frac * sat_rate
     arr_rng = np.random.default_rng(seed + 11)
@@ -373,6 +376,8 @@ def serving(torch, snlm, n_req=2000, rate_frac=0.7, seed=4000, check=32):
         "saturation_mpx_per_s": round(total_px / span_sat / 1e6, 1),
         "saturation_submit_s": round(sub_sat, 4),
         "saturation_device_p50_ms": round(float(np.percentile(dev_sat, 50)), 3),
+        "saturation_rounds": sat_rounds, "saturation_jobs_per_round": round(sat_jobs / max(sat_rounds, 1), 2),
+        "saturation_scheduler_host_us_per_round": round(sat_host_us / max(sat_rounds, 1), 1),
         "rate_req_per_s": round(rate, 1),
         "p50_ms": round(float(np.percentile(dev, 50)), 3),
         "p99_ms": round(float(np.percentile(dev, 99)), 3),
@@ -385,6 +390,38 @@ def serving(torch, snlm, n_req=2000, rate_frac=0.7, seed=4000, check=32):
         "plain_fifo_p99_ms": round(float(np.percentile(plat, 99)), 3),
         "plain_fifo_mpx_per_s": round(total_px / plain_span / 1e6, 1),
     }
+
+
+def serving_overlap(path):
+    """From a rocprofv3 kernel-trace CSV of a --serve-only run: the served
+    batched kernels (snlm_kernel launches and the staging copies) per queue,
+    the share of their busy time during which kernels of two or more rounds
+    run at once, and the most kernels running at once."""
+    import csv
+    ev = []
+    for r in csv.DictReader(open(path)):
+        name = r["Kernel_Name"]
+        if "snlm_kernel" not in name and "snlm_copy_images" not in name:
+            continue
+        ev.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r.get("Queue_Id", "?"), name))
+    if not ev:
+        return {"dispatches": 0}
+    pts = sorted([(s, 1) for s, _, _, _ in ev] + [(e, -1) for _, e, _, _ in ev])
+    busy = multi = 0
+    depth, last, peak = 0, pts[0][0], 0
+    for t, d in pts:
+        if depth >= 1:
+            busy += t - last
+        if depth >= 2:
+            multi += t - last
+        depth += d
+        peak = max(peak, depth)
+        last = t
+    queues = {}
+    for _, _, q, _ in ev:
+        queues[q] = queues.get(q, 0) + 1
+    return {"dispatches": len(ev), "queues": queues, "busy_us": round(busy / 1e3, 1),
+            "overlap_share_of_busy": round(multi / busy, 4) if busy else 0.0, "max_concurrent": peak}
 
 
 # --------------------------------------------------------------- precision --
@@ -579,6 +616,12 @@ def main():
     ap.add_argument("--no-iir", action="store_true")
     ap.add_argument("--batch-waves", type=int, default=0, metavar="N",
                     help="use N persistent waves per SIMD for the batch instead of autotuning (counter runs)")
+    ap.add_argument("--issue-rate", action="store_true",
+                    help="print the issue-rate probe of the pair body (snlm_issue_rate) and exit")
+    ap.add_argument("--serve-only", type=int, default=0, metavar="N",
+                    help="run only the serving section with N requests and print it (kernel traces)")
+    ap.add_argument("--serving-overlap", metavar="KERNEL_TRACE_CSV",
+                    help="print how the served kernels of a rocprofv3 kernel trace overlap in time (no GPU)")
     ap.add_argument("--iir-only", action="store_true",
                     help="run only the recursive-Gaussian section and print it")
     ap.add_argument("--profile-batch", action="store_true",
@@ -591,6 +634,9 @@ def main():
                                                          "COPY_WRITE_CSV", "COPY_MIB"),
                     help="write profiles/traffic_batch.json from rocprofv3 counter CSVs (no GPU)")
     a = ap.parse_args()
+    if a.serving_overlap:
+        print(json.dumps(serving_overlap(a.serving_overlap)))
+        return
     if a.write_counters:
         write_counters(a.write_counters)
         return
@@ -619,6 +665,17 @@ def main():
         return
     if a.iir_only:
         print(json.dumps({"recursive_gaussian": recursive_gaussian(torch, snlm)}), flush=True)
+        return
+    if a.issue_rate:
+        rows = {}
+        for mode, name in ((0, "fp32_body_8_instr"), (1, "pair_body_7_fp32_plus_exp"), (2, "exp_alone")):
+            for w in (1, 2, 4):
+                clk, ghz = snlm.issue_rate(mode, w)
+                rows["%s_w%d" % (name, w)] = {"clk_per_pair_per_simd": round(clk, 2), "clock_ghz": round(ghz, 3)}
+        print(json.dumps({"issue_rate": rows}), flush=True)
+        return
+    if a.serve_only:
+        print(json.dumps({"serving": serving(torch, snlm, n_req=a.serve_only, check=8)}), flush=True)
         return
     log("generating the batch workload")
     items = batch_workload(64, 128, 1024, seed=2000)

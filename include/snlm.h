@@ -300,14 +300,17 @@ int snlm_sync(snlm_ctx *ctx);
 /* Serving.  Submits a job to the context's scheduler and returns at once with
  * a ticket.  An event recorded on the context stream at the call orders the
  * job after work already queued there (img may be written by a kernel still
- * running on that stream).  The scheduler admits jobs in arrival order while
- * their snlm_serving_bytes fit what the arena has left (the HBM budget bounds
- * every byte a served job touches on the device), and runs each round of
- * admitted jobs on one of several library streams, so that a round overlaps
- * on the device with rounds already running: one launch copies every input
- * into its arena slot, the batched persistent launches compute into the
- * arena output slots, one launch copies the outputs to each job->out.  img
- * and out must stay valid until snlm_poll returns non-PENDING.
+ * running on that stream).  Whenever one of its library streams is free,
+ * the scheduler forms a round from the kernel class (S, K, kernel, order) of
+ * the oldest queued job: the queued jobs of that class, in arrival order,
+ * while their snlm_serving_bytes fit what the arena has left (the HBM budget
+ * bounds every byte a served job touches on the device); jobs of other
+ * classes keep their places.  A round overlaps on the device with rounds
+ * already running on the other streams: one launch copies every input into
+ * its arena slot, the two batched persistent launches (grids sized to the
+ * round's work) compute into the arena output slots, one launch copies the
+ * outputs to each job->out.  img and out must stay valid until snlm_poll
+ * returns non-PENDING.
  * Errors: SNLM_EINVAL, SNLM_ENOMEM (the job can never fit the arena),
  * SNLM_ECLOSED, SNLM_EDEVICE. */
 int snlm_submit(snlm_ctx *ctx, const snlm_job *job, uint64_t *ticket);
@@ -326,6 +329,12 @@ int snlm_submit_many(snlm_ctx *ctx, const snlm_job *jobs, int n, const double *a
  * copied), both timestamps taken by the GPU.  -1 if the round failed.
  * SNLM_ENOTICKET if unknown; call before the final snlm_poll. */
 int snlm_job_device_ms(snlm_ctx *ctx, uint64_t ticket, double *ms);
+
+/* Scheduler statistics of the context since its creation: rounds launched,
+ * the served jobs they carried, and the host time (microseconds) the
+ * scheduler thread spent planning and enqueueing them.  NULL outputs are
+ * skipped.  Errors: SNLM_EINVAL for a NULL context. */
+int snlm_serving_stats(snlm_ctx *ctx, uint64_t *rounds, uint64_t *jobs, double *host_us);
 
 /* SNLM_PENDING while the job runs; then its final status once (SNLM_OK or an
  * error), after which the ticket is forgotten (SNLM_ENOTICKET). */
@@ -375,6 +384,23 @@ int snlm_timing(snlm_ctx *ctx, int enable, double *batch_ms, int *batch_n, doubl
 const char *snlm_strerror(int status);
 const char *snlm_last_error(snlm_ctx *ctx);
 const char *snlm_version(void);
+
+/* Measurement helper behind the roofline figures (not part of denoising):
+ * how many clock cycles one SIMD of the current device takes per pair body
+ * of the line kernels (one lifted difference, two fused multiply-adds of the
+ * running window sum, the weight, two fused multiply-adds and two adds of
+ * the accumulation), with waves_per_simd (1, 2 or 4) waves resident on every
+ * SIMD, each running eight independent copies of the body.
+ *   mode 0  the body with the weight replaced by the window sum (FP32 only)
+ *   mode 1  the body with the weight w = exp2(-|R|) (v_exp_f32)
+ *   mode 2  v_exp_f32 alone (clk_per_pair is then cycles per exp per SIMD)
+ * *clk_per_pair: per SIMD, the cycles from its first wave's start to its
+ * last wave's end over the pair bodies its waves ran (iters x 8 each); the
+ * median over SIMDs.  *clock_ghz (optional): the shader clock, shader-clock
+ * cycles over constant-clock time summed over the waves.  Allocates and frees
+ * two small device buffers.  Errors: SNLM_EINVAL for arguments out of range,
+ * SNLM_EDEVICE for HIP failures. */
+int snlm_issue_rate(int mode, int waves_per_simd, int iters, double *clk_per_pair, double *clock_ghz);
 
 #ifdef __cplusplus
 }

@@ -77,10 +77,13 @@ def lib():
             L.snlm_denoise_batch.argtypes = [vp, jp, i]
             L.snlm_enqueue_ex.argtypes = [vp, jp]
             L.snlm_enqueue_static.argtypes = [jp, vp]
+            L.snlm_issue_rate.argtypes = [i, i, i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
             L.snlm_enqueue_batch.argtypes = [vp, jp, i]
             L.snlm_submit_many.argtypes = [vp, jp, i, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_uint64)]
             L.snlm_job_device_ms.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]
+            L.snlm_serving_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
+                                             ctypes.POINTER(ctypes.c_double)]
             L.snlm_sync.argtypes = [vp]
             L.snlm_submit.argtypes = [vp, jp, ctypes.POINTER(ctypes.c_uint64)]
             L.snlm_poll.argtypes = [vp, ctypes.c_uint64]
@@ -125,7 +128,7 @@ def lib():
             L.snlm_version.restype = ctypes.c_char_p
             for name in ("snlm_create", "snlm_destroy", "snlm_denoise", "snlm_denoise_ex",
                          "snlm_denoise_batch", "snlm_enqueue_ex", "snlm_enqueue_batch",
-                         "snlm_submit_many", "snlm_job_device_ms", "snlm_sync", "snlm_submit", "snlm_poll",
+                         "snlm_submit_many", "snlm_job_device_ms", "snlm_serving_stats", "snlm_sync", "snlm_submit", "snlm_poll",
                          "snlm_job_times", "snlm_validate", "snlm_autotune", "snlm_autotune_save",
                          "snlm_autotune_load", "snlm_plan_seg_len"):
                 getattr(L, name).restype = ctypes.c_int
@@ -484,6 +487,13 @@ class Context:
             raise SnlmError(rc, "snlm_job_device_ms")
         return v.value
 
+    def serving_stats(self):
+        """(rounds, jobs, scheduler host microseconds) since creation."""
+        r, j, us = ctypes.c_uint64(0), ctypes.c_uint64(0), ctypes.c_double(0.0)
+        self.check(lib().snlm_serving_stats(self._ptr, ctypes.byref(r), ctypes.byref(j), ctypes.byref(us)),
+                   "snlm_serving_stats")
+        return int(r.value), int(j.value), float(us.value)
+
     def job_times(self, ticket: int):
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         rc = lib().snlm_job_times(self._ptr, ctypes.c_uint64(ticket), ctypes.byref(a),
@@ -523,6 +533,16 @@ def enqueue_static(job: Job, stream=None) -> int:
     torch = _torch()
     st = stream if stream is not None else torch.cuda.current_stream()
     return lib().snlm_enqueue_static(ctypes.byref(job), ctypes.c_void_p(st.cuda_stream))
+
+
+def issue_rate(mode: int, waves_per_simd: int, iters: int = 4000):
+    """``snlm_issue_rate``: (clock cycles per pair body per SIMD, shader
+    clock lower bound in GHz) on the current device."""
+    clk, ghz = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    rc = lib().snlm_issue_rate(mode, waves_per_simd, iters, ctypes.byref(clk), ctypes.byref(ghz))
+    if rc != OK:
+        raise SnlmError(rc, "snlm_issue_rate")
+    return clk.value, ghz.value
 
 
 def denoise_batch(xs, S: int, K: int, hs, kernel: str = "box", order: str = "row_col", beta=None):

@@ -57,7 +57,8 @@ def build(jobs: int | None = None, only_s=None, verbose: bool = False, increment
     jobs = jobs or int(os.environ.get("SNLM_BUILD_JOBS", "0")) or max(1, os.cpu_count() or 1)
     s_values = list(range(0, 17)) if only_s is None else sorted(set([0] + list(only_s)))
     objs, cmds = [], []
-    dev_deps = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".hip"))]
+    # what snlm_inst.hip includes (snlm_issue.hip is a unit of its own)
+    dev_deps = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp") or f == "snlm_inst.hip"]
     for s in s_values:
         o = os.path.join(BUILD, "snlm_inst_s%d.o" % s)
         objs.append(o)
@@ -69,6 +70,9 @@ def build(jobs: int | None = None, only_s=None, verbose: bool = False, increment
     objs.append(api_o)
     cmds.append(COMMON + DEVICE_FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, "snlm_api.cpp"),
                                         "-o", api_o])
+    issue_o = os.path.join(BUILD, "snlm_issue.o")
+    objs.append(issue_o)
+    cmds.append(COMMON + DEVICE_FLAGS + ["-c", os.path.join(CSRC, "snlm_issue.hip"), "-o", issue_o])
     stubs = None
     if only_s is not None:
         # empty registration functions for the S values left out

@@ -267,6 +267,7 @@ struct ClassKey {
     bool operator<(const ClassKey& o) const {
         return std::tie(S, K, var, order) < std::tie(o.S, o.K, o.var, o.order);
     }
+    bool operator==(const ClassKey& o) const { return S == o.S && K == o.K && var == o.var && order == o.order; }
 };
 ClassKey class_of(const snlm_job& j) { return ClassKey{j.S, j.K, variant_of(j), (int)j.order}; }
 
@@ -603,15 +604,17 @@ struct snlm_ctx {
     std::map<uint64_t, std::shared_ptr<ServeJob>> jobs;
     ArenaAlloc alloc;
     std::vector<hipStream_t> serve_streams;
-    std::vector<LaunchSlot> serve_slots;
     std::vector<uint32_t*> serve_status;
-    std::vector<uint32_t*> h_serve_status;
     std::vector<hipEvent_t> ev_pool;     // timing events for submits (recycled at retirement)
     int inflight = 0;                    // admitted jobs whose round has not retired
     // per serve stream: the round's copy table (device, pinned staging)
     std::vector<char*> d_copy, h_copy;
     std::vector<size_t> copy_cap;
     hipEvent_t ev_sync = nullptr;        // end of a synchronous call on the caller's stream
+    // scheduler statistics: rounds launched, jobs they carried, host time spent
+    // planning and enqueueing them
+    uint64_t srv_rounds = 0, srv_jobs = 0;
+    double srv_host_us = 0.0;
 };
 
 namespace {
@@ -1003,8 +1006,11 @@ int batch_workers(snlm_ctx* c, const void* fn, int waves_per_simd) {
 // share continues it).  Passes that must keep whole lines (plain and Kahan
 // running sums) and jobs with an explicit segment length contribute fixed
 // segments that are never cut.
+// min_chunks_per_worker > 0 (served rounds): a class gets at most one
+// persistent workgroup per that many chunks of its work, so that a small
+// class does not launch a full grid of mostly idle workgroups.
 void plan_classes(snlm_ctx* c, const std::vector<const snlm_job*>& jobs,
-                  const std::vector<char*>& mids, std::vector<ClassPlan>& out) {
+                  const std::vector<char*>& mids, std::vector<ClassPlan>& out, int min_chunks_per_worker = 0) {
     std::map<ClassKey, size_t> idx;
     std::vector<ClassKey> keys;
     for (size_t i = 0; i < jobs.size(); ++i) {
@@ -1045,7 +1051,13 @@ void plan_classes(snlm_ctx* c, const std::vector<const snlm_job*>& jobs,
             }
             const size_t before = cp.tiles.size();
             std::vector<BatchTile> tiles;
-            balance_pass(src, batch_workers(c, cp.fn[p], waves), tiles, cp.first[p]);
+            int P = batch_workers(c, cp.fn[p], waves);
+            if (min_chunks_per_worker > 0) {
+                long chunks = 0;
+                for (const PieceSrc& q : src) chunks += q.c1 - q.c0;
+                P = (int)std::max(1L, std::min((long)P, chunks / min_chunks_per_worker));
+            }
+            balance_pass(src, P, tiles, cp.first[p]);
             for (auto& f : cp.first[p]) f += (uint32_t)before;
             for (const BatchTile& t : tiles) cp.jobs[t.job].tiles[p] += 1;
             if (!c->batch_split)  // claimed launches: longest tiles first
@@ -1265,9 +1277,7 @@ int start_scheduler(snlm_ctx* c) {
     if (c->sched_started) return SNLM_OK;
     HIP_CHECK(c, hipSetDevice(c->device));
     c->serve_streams.resize(kServeStreams, nullptr);
-    c->serve_slots.resize(kServeStreams * 4);
     c->serve_status.resize(kServeStreams, nullptr);
-    c->h_serve_status.resize(kServeStreams, nullptr);
     c->d_copy.resize(kServeStreams, nullptr);
     c->h_copy.resize(kServeStreams, nullptr);
     c->copy_cap.resize(kServeStreams, 0);
@@ -1275,7 +1285,6 @@ int start_scheduler(snlm_ctx* c) {
         HIP_CHECK(c, hipStreamCreateWithFlags(&c->serve_streams[i], hipStreamNonBlocking));
         HIP_CHECK(c, hipMalloc(&c->serve_status[i], sizeof(uint32_t)));
         HIP_CHECK(c, hipMemset(c->serve_status[i], 0, sizeof(uint32_t)));
-        HIP_CHECK(c, hipHostMalloc(&c->h_serve_status[i], sizeof(uint32_t), hipHostMallocDefault));
     }
     c->alloc.reset(c->arena_bytes);
     c->sched = std::thread(serve_loop, c);
@@ -1286,12 +1295,19 @@ int start_scheduler(snlm_ctx* c) {
 // Launches every admitted job as one round on serve stream si, after the
 // caller's stream has reached the newest job's submit (jobs are submitted in
 // order on that one stream, so its event covers the older ones):
-//   1. one copy launch stages every input into its arena slot;
-//   2. per kernel class, the two persistent launches compute from the staged
-//      input through the arena intermediate into the arena output slot
-//      (tables in slots [4*si, 4*si+4); more classes wait for a later round);
-//   3. one copy launch writes every output to the caller's buffer;
-//   4. the device status word and the round's completion event.
+//   1. one host-to-device copy brings the round's tables (staging copies and
+//      every class's jobs, tiles and workgroup shares) from pinned memory;
+//   2. one copy launch stages every input into its arena slot;
+//   3. per kernel class (the scheduler admits one per round), the two
+//      persistent launches (first pass, second pass; grids sized to the
+//      work) compute from the staged input through the arena intermediate
+//      into the arena output slot;
+//   4. one copy launch writes every output to the caller's buffer, and the
+//      round's completion event is recorded.
+// The stream's staging buffers are reused only once its previous round has
+// retired (the scheduler gives a stream a new round only then).
+constexpr int kServeChunksPerWorker = 2;  // chunks per persistent workgroup, at least
+
 int launch_round(snlm_ctx* c, std::vector<std::shared_ptr<ServeJob>>& round, int si, InFlight& fl) {
     hipStream_t st = c->serve_streams[si];
     const ServeJob* newest = round[0].get();
@@ -1320,38 +1336,76 @@ int launch_round(snlm_ctx* c, std::vector<std::shared_ptr<ServeJob>>& round, int
         cp[n + i] = {out, j.out, j.H, j.W, j.W, j.ld_out, 4, 0};
         max_rows = std::max(max_rows, j.H);
     }
-    const size_t cbytes = cp.size() * sizeof(snlm::CopyDesc);
-    if (c->copy_cap[si] < cbytes) {
+    std::vector<ClassPlan> plans;
+    plan_classes(c, js, mids, plans, kServeChunksPerWorker);
+    // layout of the round's table: copy descriptors, then per class its
+    // header, jobs, tiles and the two passes' first-tile indices
+    struct Lay {
+        size_t hdr, jobs, tiles, first0, first1;
+    };
+    std::vector<Lay> lay(plans.size());
+    size_t off = align_up(cp.size() * sizeof(snlm::CopyDesc), 64);
+    for (size_t k = 0; k < plans.size(); ++k) {
+        const ClassPlan& q = plans[k];
+        lay[k].hdr = off;
+        lay[k].jobs = align_up(off + sizeof(BatchHeader), 64);
+        lay[k].tiles = align_up(lay[k].jobs + q.jobs.size() * sizeof(BatchJob), 64);
+        lay[k].first0 = align_up(lay[k].tiles + q.tiles.size() * sizeof(BatchTile), 64);
+        lay[k].first1 = lay[k].first0 + q.first[0].size() * sizeof(uint32_t);
+        off = align_up(lay[k].first1 + q.first[1].size() * sizeof(uint32_t), 64);
+    }
+    const size_t tbytes = off;
+    if (c->copy_cap[si] < tbytes) {
         // the stream is idle (its last round retired), so nothing reads these
         if (c->d_copy[si]) HIP_CHECK(c, hipFree(c->d_copy[si]));
         if (c->h_copy[si]) HIP_CHECK(c, hipHostFree(c->h_copy[si]));
         c->d_copy[si] = c->h_copy[si] = nullptr;
         c->copy_cap[si] = 0;
-        const size_t cap = align_up(std::max(cbytes * 2, (size_t)1 << 14), kAlign);
+        const size_t cap = align_up(std::max(tbytes * 2, (size_t)1 << 16), kAlign);
         HIP_CHECK(c, hipMalloc(&c->d_copy[si], cap));
         HIP_CHECK(c, hipHostMalloc(&c->h_copy[si], cap, hipHostMallocDefault));
         c->copy_cap[si] = cap;
     }
-    std::memcpy(c->h_copy[si], cp.data(), cbytes);
-    HIP_CHECK(c, hipMemcpyAsync(c->d_copy[si], c->h_copy[si], cbytes, hipMemcpyHostToDevice, st));
+    char* h = c->h_copy[si];
+    char* d = c->d_copy[si];
+    std::memcpy(h, cp.data(), cp.size() * sizeof(snlm::CopyDesc));
+    for (size_t k = 0; k < plans.size(); ++k) {
+        const ClassPlan& q = plans[k];
+        BatchHeader hdr;
+        hdr.njobs = (int)q.jobs.size();
+        hdr.ntiles_first = q.ntiles_first;
+        hdr.ntiles = (int)q.tiles.size();
+        hdr.spin_limit = kSpinLimit;
+        std::memcpy(h + lay[k].hdr, &hdr, sizeof(hdr));
+        std::memcpy(h + lay[k].jobs, q.jobs.data(), q.jobs.size() * sizeof(BatchJob));
+        std::memcpy(h + lay[k].tiles, q.tiles.data(), q.tiles.size() * sizeof(BatchTile));
+        std::memcpy(h + lay[k].first0, q.first[0].data(), q.first[0].size() * sizeof(uint32_t));
+        std::memcpy(h + lay[k].first1, q.first[1].data(), q.first[1].size() * sizeof(uint32_t));
+    }
+    HIP_CHECK(c, hipMemcpyAsync(d, h, tbytes, hipMemcpyHostToDevice, st));
     const dim3 cgrid(std::min(max_rows, 64), (unsigned)n);
-    const snlm::CopyDesc* tab_in = (const snlm::CopyDesc*)c->d_copy[si];
+    const snlm::CopyDesc* tab_in = (const snlm::CopyDesc*)d;
     const snlm::CopyDesc* tab_out = tab_in + n;
     void* a_in[] = {(void*)&tab_in};
     HIP_CHECK(c, hipLaunchKernel((const void*)&snlm::snlm_copy_images, cgrid, dim3(256), a_in, 0, st));
-    std::vector<ClassPlan> plans;
-    plan_classes(c, js, mids, plans);
-    if (plans.size() > 4) return fail(c, SNLM_EINVAL, "too many classes in one round");
     for (size_t k = 0; k < plans.size(); ++k) {
-        LaunchSlot& sl = c->serve_slots[si * 4 + k];
-        int rc = upload_class(c, sl, plans[k], st);
-        if (!rc) rc = launch_class(c, sl, st, c->serve_status[si], false);
-        if (rc) return rc;
+        const ClassPlan& q = plans[k];
+        KernelArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.hdr = (const BatchHeader*)(d + lay[k].hdr);
+        a.jobs = (const BatchJob*)(d + lay[k].jobs);
+        a.tiles = (const BatchTile*)(d + lay[k].tiles);
+        a.status = c->serve_status[si];
+        KernelArgs a2 = a;
+        a.worker_first = (const uint32_t*)(d + lay[k].first0);
+        a2.worker_first = (const uint32_t*)(d + lay[k].first1);
+        void* k1[] = {&a};
+        void* k2[] = {&a2};
+        HIP_CHECK(c, hipLaunchKernel(q.fn[0], dim3((int)q.first[0].size() - 1), dim3(snlm::kLanes), k1, 0, st));
+        HIP_CHECK(c, hipLaunchKernel(q.fn[1], dim3((int)q.first[1].size() - 1), dim3(snlm::kLanes), k2, 0, st));
     }
     void* a_out[] = {(void*)&tab_out};
     HIP_CHECK(c, hipLaunchKernel((const void*)&snlm::snlm_copy_images, cgrid, dim3(256), a_out, 0, st));
-    HIP_CHECK(c, hipMemcpyAsync(c->h_serve_status[si], c->serve_status[si], sizeof(uint32_t),
-                                hipMemcpyDeviceToHost, st));
     if (!fl.done) HIP_CHECK(c, hipEventCreate(&fl.done));  // timed: device-side latency
     HIP_CHECK(c, hipEventRecord(fl.done, st));
     fl.stream = si;
@@ -1383,7 +1437,7 @@ void serve_loop(snlm_ctx* c) {
                 hipError_t q = hipEventQuery(flights[i].done);
                 if (q == hipErrorNotReady) continue;
                 const double t = now_us();
-                const bool dev_fail = (q != hipSuccess) || *c->h_serve_status[i] != 0;
+                const bool dev_fail = q != hipSuccess;
                 for (auto& sj : flights[i].jobs) {
                     float ms = -1.0f;
                     if (!dev_fail && hipEventElapsedTime(&ms, sj->mark->ev, flights[i].done) != hipSuccess)
@@ -1395,11 +1449,7 @@ void serve_loop(snlm_ctx* c) {
                     c->alloc.release(sj->off, sj->need);
                     --c->inflight;
                 }
-                if (dev_fail) {
-                    c->last_error = "served launch failed on the device";
-                    *c->h_serve_status[i] = 0;
-                    (void)hipMemset(c->serve_status[i], 0, sizeof(uint32_t));
-                }
+                if (dev_fail) c->last_error = "served launch failed on the device";
                 flights[i].jobs.clear();
                 busy[i] = false;
             }
@@ -1410,21 +1460,28 @@ void serve_loop(snlm_ctx* c) {
                     free_stream = i;
                     break;
                 }
-            if (free_stream >= 0) {
-                std::map<ClassKey, int> classes;
-                while (!c->pending.empty()) {
-                    auto& sj = c->pending.front();
-                    const ClassKey fn = class_of(sj->job);
-                    if (!classes.count(fn) && classes.size() >= 4) break;
+            if (free_stream >= 0 && !c->pending.empty()) {
+                // the kernel class of the oldest queued job goes next: its
+                // queued jobs are admitted in arrival order while they fit
+                // (the others keep their places), so that a round is one
+                // pair of persistent launches over as much work as possible
+                const ClassKey head = class_of(c->pending.front()->job);
+                std::deque<std::shared_ptr<ServeJob>> rest;
+                bool full = false;
+                for (auto& sj : c->pending) {
                     size_t off;
-                    if (!c->alloc.alloc(sj->need, &off)) break;
+                    if (full || !(class_of(sj->job) == head) || !c->alloc.alloc(sj->need, &off)) {
+                        // a job of the class that does not fit closes the round (arrival order)
+                        if (!full && class_of(sj->job) == head) full = true;
+                        rest.push_back(sj);
+                        continue;
+                    }
                     sj->off = off;
                     sj->t_admit = t;
-                    classes[fn] = 1;
                     round.push_back(sj);
-                    c->pending.pop_front();
                     ++c->inflight;
                 }
+                c->pending.swap(rest);
             }
             bool any_busy = false;
             for (int i = 0; i < kServeStreams; ++i) any_busy = any_busy || busy[i];
@@ -1438,8 +1495,12 @@ void serve_loop(snlm_ctx* c) {
             }
         }
         InFlight& fl = flights[free_stream];
+        const double t_round = now_us();
         int rc = launch_round(c, round, free_stream, fl);
         std::lock_guard<std::mutex> lk(c->mu);
+        c->srv_rounds += 1;
+        c->srv_jobs += round.size();
+        c->srv_host_us += now_us() - t_round;
         if (rc != SNLM_OK) {
             // nothing of this round may still run: wait for what was enqueued
             (void)hipStreamSynchronize(c->serve_streams[free_stream]);
@@ -1678,13 +1739,10 @@ int snlm_destroy(snlm_ctx* c) {
     }
     (void)hipStreamSynchronize(c->work);
     for (auto& s : c->slots) free_slot(s);
-    for (auto& s : c->serve_slots) free_slot(s);
     for (auto st : c->serve_streams)
         if (st) (void)hipStreamDestroy(st);
     for (auto p : c->serve_status)
         if (p) (void)hipFree(p);
-    for (auto p : c->h_serve_status)
-        if (p) (void)hipHostFree(p);
     for (auto p : c->d_copy)
         if (p) (void)hipFree(p);
     for (auto p : c->h_copy)
@@ -2462,6 +2520,15 @@ int snlm_job_device_ms(snlm_ctx* c, uint64_t ticket, double* ms) {
     auto it = c->jobs.find(ticket);
     if (it == c->jobs.end()) return SNLM_ENOTICKET;
     *ms = it->second->dev_ms;
+    return SNLM_OK;
+}
+
+int snlm_serving_stats(snlm_ctx* c, uint64_t* rounds, uint64_t* jobs, double* host_us) {
+    if (!c) return SNLM_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (rounds) *rounds = c->srv_rounds;
+    if (jobs) *jobs = c->srv_jobs;
+    if (host_us) *host_us = c->srv_host_us;
     return SNLM_OK;
 }
 

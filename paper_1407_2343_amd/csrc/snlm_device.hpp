@@ -141,12 +141,10 @@ constexpr int kTileOut = kLanes * kStage;   // floats of LDS for the output tile
 // 16-byte vectors per line that hold COUNT consecutive FP32 samples starting
 // anywhere in the first vector.
 constexpr int win_vectors(int count) { return (count + 6) / 4; }
-// LDS floats of a row kernel: the chunk tiles, or the pre-chunk's sample
-// window of COUNT samples per line when that is larger.
-constexpr int row_lds_floats(int count) {
-    return kTileIn + kTileOut > kLanes * 4 * win_vectors(count) ? kTileIn + kTileOut
-                                                                 : kLanes * 4 * win_vectors(count);
-}
+// LDS floats of a row kernel: the chunk tiles, then a region for the
+// pre-chunk's sample window of COUNT samples per line (so that the first
+// chunk's loads can fly while the window is read).
+constexpr int row_lds_floats(int count) { return kTileIn + kTileOut + kLanes * 4 * win_vectors(count); }
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
@@ -179,6 +177,7 @@ struct LineIO {
     bool stage_out;      // lines contiguous and 16-byte aligned in the output
     float* tile_in;      // input tile (kTileIn floats of LDS)
     float* tile_out;     // output tile (kTileOut floats of LDS)
+    float* tile_win;     // pre-chunk window region (row kernels)
 
     // count samples starting at position p (reflected), into v[0..count)
     // (the lane's line start is the per-lane offset, the position the
@@ -203,34 +202,41 @@ struct LineIO {
     }
 
     // The pre-chunk's sample window: COUNT samples from position p into v.
-    // Rows inside the line go through LDS (the whole tile region: nothing
-    // else is in flight there at a tile's start) with 16-byte loads along
-    // each row, instead of COUNT per-lane loads that touch a cache line per
-    // lane each.
+    // Rows inside the line go through the LDS window region with 16-byte
+    // loads along each row, instead of COUNT per-lane loads that touch a
+    // cache line per lane each.  start_window issues the loads;
+    // finish_window waits for them (the first chunk's five tile loads,
+    // issued in between, may still fly) and reads them out.
     template <int COUNT>
-    __device__ __forceinline__ void load_window(int p, float* v) const {
-        if (!(stage_in && !f16 && p >= 0 && p + COUNT <= n)) {
-            load<COUNT>(p, v);
-            return;
-        }
+    __device__ __forceinline__ bool window_staged(int p) const {
+        return stage_in && !f16 && p >= 0 && p + COUNT <= n;
+    }
+    template <int COUNT>
+    __device__ __forceinline__ void start_window(int p) const {
         constexpr int V = win_vectors(COUNT);
         typedef __attribute__((address_space(3))) void* lds_ptr;
         // load j = lane + 64 r covers line j / V, vector j % V of that line,
-        // and lands at LDS byte 16 j
+        // and lands at LDS byte 16 j of the window region
 #pragma unroll
         for (int r = 0; r < V; ++r) {
             const int j = lane + 64 * r;
             const int line = min(line0 + j / V, nlines - 1);
             const int e = ((line * in_line + p) & ~3) + 4 * (j % V);
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, (lds_ptr)(tile_in + 256 * r), 16, e * 4, 0, 0, 0);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, (lds_ptr)(tile_win + 256 * r), 16, e * 4, 0, 0, 0);
         }
-        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    }
+    template <int COUNT>
+    __device__ __forceinline__ void finish_window(int p, float* v, bool five_loads_after) const {
+        constexpr int V = win_vectors(COUNT);
+        if (five_loads_after)
+            __builtin_amdgcn_s_waitcnt(0x0F75);  // vmcnt(5): the first chunk's tile loads may fly
+        else
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
         __syncthreads();
         const int line = min(line0 + lane, nlines - 1);
         const int m = (line * in_line + p) & 3;
 #pragma unroll
-        for (int t = 0; t < COUNT; ++t) v[t] = tile_in[lane * 4 * V + m + t];
-        __syncthreads();
+        for (int t = 0; t < COUNT; ++t) v[t] = tile_win[lane * 4 * V + m + t];
     }
 
     // Whether the chunk of samples [p, p + kChunk) goes through the LDS tile.
@@ -373,11 +379,19 @@ __device__ __forceinline__ void run_segment(const PassDesc& d, const LineIO& io,
     // Column passes: the first chunk's loads go out first; the pre-chunk
     // waits for the window's, so the loop finds them complete and its own
     // wait at the top counts only the previous iteration's loads.  Row
-    // passes: the window goes through the LDS tile region first.
+    // passes: the window's loads into its LDS region go out first, the first
+    // chunk's tile loads behind them.
     int c0 = seg_a - C;
     if (io.stage_in) {
-        io.template load_window<NX>(c0 - K - 1, xs);
-        io.issue_chunk(seg_a + S + K, nx);
+        if (io.template window_staged<NX>(c0 - K - 1)) {
+            io.template start_window<NX>(c0 - K - 1);
+            const bool tile_loads = io.chunk_staged(seg_a + S + K);
+            io.issue_chunk(seg_a + S + K, nx);
+            io.template finish_window<NX>(c0 - K - 1, xs, tile_loads);
+        } else {
+            io.template load<NX>(c0 - K - 1, xs);
+            io.issue_chunk(seg_a + S + K, nx);
+        }
     } else {
         io.issue_chunk(seg_a + S + K, nx);
         io.template load<NX>(c0 - K - 1, xs);
@@ -523,6 +537,7 @@ __device__ __forceinline__ LineIO make_io(const PassDesc& d, int line0, int lane
                    ((uintptr_t)d.out & 15) == 0;
     io.tile_in = tiles;
     io.tile_out = tiles + kTileIn;
+    io.tile_win = tiles + kTileIn + kTileOut;
     return io;
 }
 

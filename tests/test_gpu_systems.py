@@ -72,6 +72,36 @@ def test_batch_equals_plain(mode):
     ctx.close()
 
 
+@pytest.mark.parametrize("order", ["row_col", "col_row"])
+def test_batch_short_last_groups(order):
+    """Images whose last line group holds few lines (H or W = 64 q + r with
+    r in 1..33; the lanes past r repeat the last line and store its values
+    again).  Every output is bitwise its plain launch (box and Gaussian, FP32
+    and FP16) and within 1e-3 of the FP64 oracle."""
+    import torch
+    import paper_1407_2343_amd as snlm
+    shapes = [(65, 128), (66, 1000), (95, 129), (96, 255), (97, 300), (128 + 31, 190), (130, 65), (300, 129),
+              (1000, 129), (1, 400)]
+    ctx = _ctx(64 << 20)
+    for kern, dt in (("box", "f32"), ("gauss", "f16")):
+        jobs, keep = [], []
+        for i, (H, W) in enumerate(shapes):
+            img = noisy_image(H, W, 20.0, seed=800 + i)
+            x = torch.from_numpy(img.astype(np.float16 if dt == "f16" else np.float32)).to("cuda:0")
+            o = torch.full((H, W), -5.0, device="cuda:0")
+            jobs.append(ctx.job_for(x, o, 10, 3, 200.0, kern, order))
+            keep.append((x, o))
+        ctx.denoise_jobs(jobs, sync=True)
+        for i, ((x, o), (H, W)) in enumerate(zip(keep, shapes)):
+            say("short last group", kern, dt, order, (H, W))
+            alone = ctx.denoise(x, 10, 3, 200.0, kern, order, sync=True)
+            assert torch.equal(o, alone), (H, W)
+            if i % 3 == 0:
+                ref = oracle.snlm(x.cpu().numpy().astype(np.float64), 10, 3, 200.0, kern, order)
+                assert max_abs(o.cpu().numpy(), ref) <= TOL, (H, W)
+    ctx.close()
+
+
 def test_batch_mixed_classes():
     """Several (S, K, kernel, order) classes in one batch call."""
     import torch
