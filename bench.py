@@ -273,7 +273,7 @@ def counters_from_profiles():
 
 
 # ----------------------------------------------------------------- serving --
-def serving(torch, snlm, n_req=2000, rate_frac=0.7, seed=4000, check=32):
+def serving(torch, snlm, n_req=2000, rate_frac=0.7, seed=4000, check=32, fifo=True):
     """2000 requests (sizes log-uniform 64..2048 per axis, sigma U[10,40],
     S in {5,10,15}, K in {2,3,4}, box/Gauss and both orders 50/50), inputs
     generated on the device before timing and submitted by the library's own
@@ -345,7 +345,7 @@ def serving(torch, snlm, n_req=2000, rate_frac=0.7, seed=4000, check=32):
     host, dev, span, _ = run(list(arrivals), jobs)
     torch.cuda.synchronize()
     # served results against plain launches of the same jobs, bitwise
-    pick = np.random.default_rng(seed + 13).choice(n_req, size=min(check, n_req), replace=False)
+    pick = np.random.default_rng(seed + 13).choice(n_req, size=min(check, n_req), replace=False) if check else []
     served = [outs[i].clone() for i in pick]
     srv.close()
     plain = snlm.Context(arena_bytes=arena)
@@ -354,22 +354,7 @@ def serving(torch, snlm, n_req=2000, rate_frac=0.7, seed=4000, check=32):
         plain.denoise_job_sync(job_list[i])
         same = same and bool(torch.equal(outs[i], got))
 
-    # FIFO plain launches at the same arrival times
-    for j in job_list[:64]:
-        plain.denoise_job(j)
-    plain.sync()
-    t_start = time.perf_counter()
-    plat = []
-    for j, a in zip(job_list, arrivals):
-        while time.perf_counter() - t_start < a:
-            pass
-        plain.denoise_job(j)
-        plain.sync()
-        plat.append((time.perf_counter() - t_start - a) * 1e3)
-    plain_span = time.perf_counter() - t_start
-    plain.close()
-    plat = np.array(plat)
-    return {
+    rec = {
         "requests": n_req, "pixels": int(total_px), "arena_bytes": arena,
         "admission": "staged input + FP32 intermediate + FP32 output slot per job within the arena",
         "saturation_req_per_s": round(sat_rate, 1),
@@ -386,10 +371,31 @@ def serving(torch, snlm, n_req=2000, rate_frac=0.7, seed=4000, check=32):
         "host_p99_ms": round(float(np.percentile(host, 99)), 3),
         "mpx_per_s": round(total_px / span / 1e6, 1),
         "checked_requests": len(pick), "checked_bitwise_equal_to_plain": same,
+    }
+    if not fifo:
+        plain.close()
+        return rec
+    # FIFO plain launches at the same arrival times
+    for j in job_list[:64]:
+        plain.denoise_job(j)
+    plain.sync()
+    t_start = time.perf_counter()
+    plat = []
+    for j, a in zip(job_list, arrivals):
+        while time.perf_counter() - t_start < a:
+            pass
+        plain.denoise_job(j)
+        plain.sync()
+        plat.append((time.perf_counter() - t_start - a) * 1e3)
+    plain_span = time.perf_counter() - t_start
+    plain.close()
+    plat = np.array(plat)
+    rec.update({
         "plain_fifo_p50_ms": round(float(np.percentile(plat, 50)), 3),
         "plain_fifo_p99_ms": round(float(np.percentile(plat, 99)), 3),
         "plain_fifo_mpx_per_s": round(total_px / plain_span / 1e6, 1),
-    }
+    })
+    return rec
 
 
 def serving_overlap(path):
@@ -675,7 +681,8 @@ def main():
         print(json.dumps({"issue_rate": rows}), flush=True)
         return
     if a.serve_only:
-        print(json.dumps({"serving": serving(torch, snlm, n_req=a.serve_only, check=8)}), flush=True)
+        # the served phases only (no bitwise check, no FIFO baseline): for kernel traces
+        print(json.dumps({"serving": serving(torch, snlm, n_req=a.serve_only, check=0, fifo=False)}), flush=True)
         return
     log("generating the batch workload")
     items = batch_workload(64, 128, 1024, seed=2000)

@@ -58,3 +58,52 @@ def test_traffic_record(tmp_path):
     assert rec["hbm_bytes_per_step"] == int(row["bytes"] + col["bytes"])
     assert rec["source_sha256"] == bench.source_sha()
     assert json.load(open(out)) == rec
+
+
+def test_counter_record(tmp_path):
+    """Counters of two groups (two CSVs) merge per kernel; each averages its
+    last 3 dispatches; per-pair figures divide lane-instructions by pixels x S."""
+    import numpy as np
+    from paper_1407_2343_amd.synth import batch_workload
+    row_k = "void snlm::snlm_kernel<10, 3, false, false, true, true>(snlm::KernelArgs)"
+    col_k = "void snlm::snlm_kernel<10, 3, false, false, true, false>(snlm::KernelArgs)"
+    pairs = sum(img.size for img, _ in batch_workload(64, 128, 1024, seed=2000)) * 10
+    a, b = str(tmp_path / "a.csv"), str(tmp_path / "b.csv")
+    rows_a = [(d, k, c, v) for k in (row_k, col_k)
+              for d in range(1, 6)
+              for c, v in (("SQ_INSTS_VALU", pairs * 11 / 64 if d > 2 else 1.0),
+                           ("SQ_INSTS_VALU_TRANS_F32", pairs / 64 if d > 2 else 1.0))]
+    rows_b = [(d, k, c, v) for k in (row_k, col_k)
+              for d in range(11, 16)
+              for c, v in (("SQ_WAVE_CYCLES", 1000.0), ("SQ_WAIT_INST_ANY", 250.0), ("SQ_ACTIVE_INST_VALU", 500.0))]
+    for path, rows in ((a, rows_a), (b, rows_b)):
+        with open(path, "w", newline="") as f:
+            w = csv.DictWriter(f, fieldnames=FIELDS)
+            w.writeheader()
+            for d, k, c, v in rows:
+                w.writerow({"Dispatch_Id": d, "Kernel_Name": k, "Counter_Name": c, "Counter_Value": v})
+    out = str(tmp_path / "counters.json")
+    rec = bench.write_counters([a, b], out_path=out)
+    for k in (row_k, col_k):
+        lr = rec["launches"][k]
+        assert np.isclose(lr["valu_per_pair"], 11.0) and np.isclose(lr["trans_per_pair"], 1.0)
+        assert lr["wait_inst_share"] == 0.25 and lr["valu_active_share"] == 0.5
+    assert np.isclose(rec["step"]["valu_per_pair"], 11.0)
+    assert rec["source_sha256"] == bench.source_sha()
+
+
+def test_serving_overlap(tmp_path):
+    """Kernel intervals [0,10) and [5,20) on two queues, plus a kernel of
+    another library: busy 20 us, two at once for 5 us."""
+    path = str(tmp_path / "trace.csv")
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Queue_Id", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        w.writerow({"Kernel_Name": "snlm_kernel<5,2>", "Queue_Id": 1, "Start_Timestamp": 0, "End_Timestamp": 10000})
+        w.writerow({"Kernel_Name": "snlm_copy_images", "Queue_Id": 2, "Start_Timestamp": 5000,
+                    "End_Timestamp": 20000})
+        w.writerow({"Kernel_Name": "elementwise_kernel", "Queue_Id": 3, "Start_Timestamp": 0,
+                    "End_Timestamp": 50000})
+    r = bench.serving_overlap(path)
+    assert r["dispatches"] == 2 and r["busy_us"] == 20.0 and r["max_concurrent"] == 2
+    assert r["overlap_share_of_busy"] == 0.25
