@@ -568,13 +568,14 @@ def recursive_gaussian(torch, snlm, n=2048, sigma=30.0):
         ref = oracle.snlm(xr, S, 0, h_for(beta), "gauss_iir", "row_col", beta=beta)
         rec[name]["max_abs_vs_oracle"] = float(np.max(np.abs(outs[name] - ref)))
     # HBM roofline of the recursive path at beta = 2 (both passes): per pass,
-    # the forward recursion writes S (n + L + S) FP32 values per line and the
-    # backward reads them back and writes S (n + S) distances, which the NLM
-    # pass reads; x is read twice and y written once; the row pass adds a
-    # transposed copy of its input (read + write).  The method's own minimum
-    # is x in and y out.
+    # the forward recursion reads x and writes its FP64 state at every block
+    # start (3 S ((n + L - 1) / 16 + 2) words per line), the NLM kernel reads
+    # the states back (once each at least: segment warm-ups re-read a few
+    # blocks), reads x and writes y; the row pass adds a transposed copy of
+    # its input (read + write).  The method's own minimum is x in and y out.
     L = int(np.ceil(6 * 2.0)) + S + 3
-    per_pass = 4 * n * (2 * S * (n + L + S) + 2 * S * (n + S) + 3 * n)
+    nblk = (n + L - 1) // 16 + 2
+    per_pass = n * (4 * 3 * n + 2 * 8 * 3 * S * nblk)
     staged = 2 * per_pass + 8 * n * n
     method = 2 * 8 * n * n  # x in and y out, per pass
     ms2 = rec["iir_beta2"]["ms"]
@@ -582,9 +583,9 @@ def recursive_gaussian(torch, snlm, n=2048, sigma=30.0):
     rec["iir_beta2"]["roofline"] = {
         "bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s", "frac": round(gbs / 8000.0, 4),
         "bytes": int(method), "bytes_are": "the method's own: x in and y out (4 + 4 B per pixel) per pass, "
-        "over the whole-path time (seven launches)",
+        "over the whole-path time (five launches)",
         "staged_bytes": int(staged), "staged_gb_per_s": round(staged / (ms2 * 1e-3) / 1e9, 1),
-        "staged_are": "w and distances written and read once, x read twice, y written once per pass, plus "
+        "staged_are": "forward states written and read once, x read twice, y written once per pass, plus "
         "the row pass's transposed input"}
     rec["iir_beta2"]["max_abs_vs_exact_fir_K6"] = float(np.max(np.abs(outs["iir_beta2"] - outs["fir_beta2_K6"])))
     rec["iir_beta2"]["rms_vs_exact_fir_K6"] = float(np.sqrt(np.mean((outs["iir_beta2"] - outs["fir_beta2_K6"]) ** 2)))

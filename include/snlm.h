@@ -72,10 +72,13 @@ enum {
  *                   reach).  Cost per sample is independent of beta; K only
  *                   sets the default beta = K / 2.  0.5 <= beta <= 256.  Runs
  *                   in snlm_denoise, snlm_denoise_ex and snlm_denoise3d (other
- *                   entry points return SNLM_EINVAL); each pass keeps
- *                   S (n + L + S) FP32 distances per line in a library-owned
- *                   device buffer (grown on demand, held until snlm_destroy),
- *                   which must stay below 2 GiB. */
+ *                   entry points return SNLM_EINVAL); each pass keeps the
+ *                   forward recursion's FP64 state at every 16th position,
+ *                   3 S ((n + L - 1) / 16 + 2) values per line, and for a
+ *                   pass along rows an FP32 transposed copy of its input, in
+ *                   a library-owned device buffer (grown on demand, held
+ *                   until snlm_destroy) whose two regions must each stay
+ *                   below 2 GiB. */
 typedef enum { SNLM_BOX = 0, SNLM_GAUSS = 1, SNLM_GAUSS_IIR = 2 } snlm_kernel;
 typedef enum { SNLM_ROW_COL = 0, SNLM_COL_ROW = 1 } snlm_order;
 typedef enum { SNLM_F32 = 0, SNLM_F16 = 1 } snlm_dtype;
@@ -376,8 +379,9 @@ int snlm_plan_seg_len(snlm_ctx *ctx, const snlm_job *job, int pass);
  * pass launch; enable = 0 stops, waits for the recorded events and returns the
  * summed device time of batched launches in *batch_ms (count in *batch_n) and
  * of direct pass launches in *direct_ms (count in *direct_n).  For the
- * recursive Gaussian kernel a pass's events bracket its NLM launch only (the
- * recursions before it are not included).  Pointers may be NULL. */
+ * recursive Gaussian kernel a pass's events bracket all of its launches (the
+ * transposed copy of a row pass's input, the forward recursion, and the
+ * backward recursion with the NLM).  Pointers may be NULL. */
 int snlm_timing(snlm_ctx *ctx, int enable, double *batch_ms, int *batch_n, double *direct_ms,
                 int *direct_n);
 

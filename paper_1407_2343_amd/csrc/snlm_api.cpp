@@ -277,9 +277,16 @@ double iir_beta(const snlm_job& j) { return j.beta > 0.0f ? (double)j.beta : j.K
 // Samples the recursion runs beyond each end of a line.
 int iir_reach(int S, double beta) { return (int)std::ceil(6.0 * beta) + S + 3; }
 
-// Bytes of the distances of one pass: lines of n samples.
-double iir_dist_bytes(int n, int nlines, int S, double beta) {
-    return (double)S * (n + iir_reach(S, beta) + S) * (double)nlines * 4.0;
+// Blocks of 16 positions per (offset, line) whose forward states a pass
+// stores: blocks -1 .. (n + L - 1) / 16.
+int iir_blocks(int n, int S, double beta) { return (n + iir_reach(S, beta) - 1) / kChunk + 2; }
+
+// Whether a region of one pass's library buffer (the forward states, or the
+// transposed FP32 input of a row pass) would reach 2 GiB: lines of n samples.
+bool iir_too_big(int n, int nlines, int S, double beta) {
+    const double states = (double)S * iir_blocks(n, S, beta) * 3.0 * nlines * 8.0;
+    const double xt = (double)n * nlines * 4.0;
+    return states >= 2147483647.0 || xt >= 2147483647.0;
 }
 
 // Largest modulus of the recursion's poles, the roots of z^3 - a1 z^2 - a2 z
@@ -344,9 +351,8 @@ const char* check_job(const snlm_job* j) {
     if (j->kernel == SNLM_GAUSS_IIR) {
         const double beta = iir_beta(*j);
         if (!(beta >= 0.5 && beta <= 256.0)) return "the recursive Gaussian needs 0.5 <= beta <= 256";
-        if (iir_dist_bytes(j->W, j->H, j->S, beta) >= 2147483647.0 ||
-            iir_dist_bytes(j->H, j->W, j->S, beta) >= 2147483647.0)
-            return "recursive-Gaussian distances of a pass exceed 2 GiB";
+        if (iir_too_big(j->W, j->H, j->S, beta) || iir_too_big(j->H, j->W, j->S, beta))
+            return "recursive-Gaussian buffers of a pass exceed 2 GiB";
     }
     const size_t esz = j->dtype == SNLM_F16 ? 2 : 4;
     const double in_bytes = ((double)(j->H - 1) * j->ld_in + j->W) * esz;
@@ -716,17 +722,38 @@ int ensure_buffer(snlm_ctx* c, float** buf, size_t* cap, size_t need) {
     return SNLM_OK;
 }
 
-// One recursive-Gaussian pass (S >= 1): the forward and backward recursions
-// of every offset, in segments, then the 1D NLM from the distances.  One
-// library-owned buffer holds w (n + L + S positions per offset and line) and
-// the distances (n + S), each region below 2 GiB.
-// Bytes of the library-owned buffer one recursive-Gaussian pass uses: the
-// distances, w, and (row passes) the transposed input, each region aligned.
+// One recursive-Gaussian pass (S >= 1): the forward recursion of every
+// offset, which stores its state at each block start, then the kernel that
+// recomputes each block, runs the backward recursion and the 1D NLM.
+// Bytes of the library-owned buffer one pass uses: the forward states, and
+// (row passes) the transposed input, each region aligned.
 size_t iir_pass_bytes(const snlm_job& j, const PassDesc& d, bool rows) {
-    const size_t nvw = (size_t)d.n + iir_reach(j.S, iir_beta(j)) + j.S, nvd = (size_t)d.n + j.S;
-    const size_t wb = (size_t)j.S * nvw * d.nlines * sizeof(float);
-    const size_t db = (size_t)j.S * nvd * d.nlines * sizeof(float);
-    return align_up(db, kAlign) + align_up(wb, kAlign) + (rows ? (size_t)d.n * d.nlines * sizeof(float) : 0);
+    const size_t cb = (size_t)j.S * iir_blocks(d.n, j.S, iir_beta(j)) * 3 * d.nlines * sizeof(double);
+    return align_up(cb, kAlign) + (rows ? (size_t)d.n * d.nlines * sizeof(float) : 0);
+}
+
+// Outputs per segment of the NLM kernel: the number of segments that
+// minimises (rounds of workgroups) x (blocks each workgroup walks: its
+// outputs, the backward warm-up W and the block below), with resident
+// workgroups counted for 256 compute units and the kernel's LDS.  A function
+// of the job alone.
+int iir_nlm_seg(int n, int ngroups, int S, int W) {
+    const int lds = (96 + 32 * S) * 64 * 4;
+    const long slots = 256L * std::max(1, std::min(32 / S, 163840 / lds));
+    const int nblocks = (n + kChunk - 1) / kChunk;
+    long best = -1;
+    int best_seg = nblocks * kChunk;
+    for (int nseg = 1; nseg <= nblocks; ++nseg) {
+        const int per = (nblocks + nseg - 1) / nseg;  // blocks of outputs per segment
+        const int used = (nblocks + per - 1) / per;
+        const long rounds = ((long)ngroups * used + slots - 1) / slots;
+        const long cost = rounds * (per + W / kChunk + 1);
+        if (best < 0 || cost < best) {
+            best = cost;
+            best_seg = per * kChunk;
+        }
+    }
+    return best_seg;
 }
 
 int iir_pass(snlm_ctx* c, const snlm_job& j, const PassDesc& d, bool rows, hipStream_t st) {
@@ -736,31 +763,43 @@ int iir_pass(snlm_ctx* c, const snlm_job& j, const PassDesc& d, bool rows, hipSt
     ia.pass = d;
     ia.S = j.S;
     ia.L = iir_reach(j.S, beta);
-    iir_coeffs(beta, &ia.B, &ia.a1, &ia.a2, &ia.a3);
-    ia.scale = std::sqrt(2.0 * M_PI) * beta;
-    ia.W = (iir_warmup(ia.a1, ia.a2, ia.a3) + kChunk - 1) / kChunk * kChunk;  // chunk-aligned segments
-    const int nvw = d.n + ia.L + j.S, nvd = d.n + j.S;
-    // Segments: about 2048 waves per recursion (two per SIMD: each wave is a
-    // serial chain; more segments cost more warm-up reads), but at least 2W
-    // long (warm-up <= 1/3 of a wave's steps).  A function of the job alone.
+    double B = 0.0;
+    iir_coeffs(beta, &B, &ia.a1, &ia.a2, &ia.a3);
+    // the kernels run the recursions on w / B and y / B^2 (no multiply by B
+    // per step): the steady states take 1 / B, the distance sqrt(2 pi) beta B^2
+    ia.inv_B = 1.0 / B;
+    ia.scale = std::sqrt(2.0 * M_PI) * beta * B * B;
+    ia.W = (iir_warmup(ia.a1, ia.a2, ia.a3) + kChunk - 1) / kChunk * kChunk;  // whole blocks
+    ia.nblk = iir_blocks(d.n, j.S, beta);
+    // Forward segments: about 2048 waves (two per SIMD: each wave is a serial
+    // chain; more segments cost more warm-up), but at least 2W long; a
+    // segment with warm-up walks fwd_blocks + W / 16 block starts, one then
+    // whole runs of 4 (the kernel's unrolled loop), so fwd_blocks + W / 16 - 1
+    // is made a multiple of 4.
     const int per_line = std::max(1, (2048 + d.ngroups * j.S - 1) / (d.ngroups * j.S));
-    ia.seg = std::max(2 * ia.W, ((nvw + per_line - 1) / per_line + kChunk - 1) / kChunk * kChunk);
-    ia.nseg_f = (nvw + ia.seg - 1) / ia.seg;
-    ia.nseg_b = (nvd + ia.seg - 1) / ia.seg;
-    const size_t wb = (size_t)j.S * nvw * d.nlines * sizeof(float);
-    const size_t db = (size_t)j.S * nvd * d.nlines * sizeof(float);
-    if (wb >= 2147483647u) return fail(c, SNLM_EINVAL, "recursive-Gaussian distances of a pass exceed 2 GiB");
-    const size_t w_off = align_up(db, kAlign);
-    const size_t xt_off = w_off + align_up(wb, kAlign);
+    ia.fwd_blocks = std::max(2 * ia.W / kChunk, (ia.nblk + per_line - 1) / per_line);
+    ia.fwd_blocks += (4 - (ia.fwd_blocks + ia.W / kChunk - 1) % 4) % 4;
+    ia.nseg_f = (ia.nblk + ia.fwd_blocks - 1) / ia.fwd_blocks;
+    ia.seg = iir_nlm_seg(d.n, d.ngroups, j.S, ia.W);
+    const int nseg = (d.n + ia.seg - 1) / ia.seg;
+    const size_t cb = (size_t)j.S * ia.nblk * 3 * d.nlines * sizeof(double);
+    if (cb >= 2147483647u) return fail(c, SNLM_EINVAL, "recursive-Gaussian buffers of a pass exceed 2 GiB");
+    const size_t xt_off = align_up(cb, kAlign);
     const size_t xtb = rows ? (size_t)d.n * d.nlines * sizeof(float) : 0;
     int rc = ensure_buffer(c, &c->d_iir, &c->iir_cap, iir_pass_bytes(j, d, rows));  // = xt_off + xtb
     if (rc) return rc;
-    ia.dist = c->d_iir;
-    ia.dist_bytes = (uint32_t)db;
-    ia.w = (float*)((char*)c->d_iir + w_off);
-    ia.w_bytes = (uint32_t)wb;
+    ia.ck = (double*)c->d_iir;
+    ia.ck_bytes = (uint32_t)cb;
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    if (c->timing) {
+        rc = timing_pair(c, &ev);
+        if (rc) return rc;
+        HIP_CHECK(c, hipEventRecord(ev.first, st));
+    }
     if (rows) {
-        // the forward recursion reads a transposed FP32 copy of the input
+        // both recursions read a transposed FP32 copy of the input (coalesced
+        // samples); the outputs keep the pass's own addressing (rows never
+        // use two-level line addresses)
         snlm::IirTransposeArgs ta;
         std::memset(&ta, 0, sizeof(ta));
         ta.pass = d;
@@ -779,29 +818,11 @@ int iir_pass(snlm_ctx* c, const snlm_job& j, const PassDesc& d, bool rows, hipSt
         t.split = 0;
     }
     void* args[] = {&ia};
-    HIP_CHECK(c, hipLaunchKernel((const void*)&snlm::snlm_iir_fwd_kernel<4>, dim3(d.ngroups * j.S * ia.nseg_f),
-                                 dim3(snlm::kLanes), args, 0, st));
-    HIP_CHECK(c, hipLaunchKernel((const void*)&snlm::snlm_iir_bwd_kernel<kChunk>,
-                                 dim3(d.ngroups * j.S * ia.nseg_b), dim3(snlm::kLanes), args, 0, st));
+    const void* fwd = ia.pass.in_f16 ? (const void*)&snlm::snlm_iir_fwd_kernel<4, true>
+                                     : (const void*)&snlm::snlm_iir_fwd_kernel<4, false>;
+    HIP_CHECK(c, hipLaunchKernel(fwd, dim3(d.ngroups * j.S * ia.nseg_f), dim3(snlm::kLanes), args, 0, st));
     init_registry();
-    snlm::IirNlmArgs na;
-    std::memset(&na, 0, sizeof(na));
-    // a row pass reads the transposed copy here too: its samples then load
-    // coalesced, and only its outputs go through the LDS tile (rows never use
-    // two-level line addresses, so the outputs' addressing is unchanged)
-    na.pass = rows ? ia.pass : d;
-    na.dist = ia.dist;
-    na.dist_bytes = ia.dist_bytes;
-    na.nv = nvd;
-    void* nargs[] = {&na};
-    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
-    if (c->timing) {
-        rc = timing_pair(c, &ev);
-        if (rc) return rc;
-        HIP_CHECK(c, hipEventRecord(ev.first, st));
-    }
-    HIP_CHECK(c, hipLaunchKernel(g_reg.iir[j.S][rows ? 1 : 0], dim3(d.ngroups * d.nseg), dim3(snlm::kLanes), nargs,
-                                 0, st));
+    HIP_CHECK(c, hipLaunchKernel(g_reg.iir[j.S], dim3(d.ngroups * nseg), dim3(snlm::kLanes * j.S), args, 0, st));
     if (c->timing) {
         HIP_CHECK(c, hipEventRecord(ev.second, st));
         c->t_direct.push_back(ev);
@@ -2070,8 +2091,8 @@ int snlm_denoise3d(snlm_ctx* c, const void* img, int ld_in, snlm_dtype dtype, fl
     if (kernel == SNLM_GAUSS_IIR)
         for (int axis = 0; axis < 3; ++axis) {
             const int n = axis == 0 ? W : (axis == 1 ? H : D);
-            if (iir_dist_bytes(n, (int)((long)D * H * W / n), S, iir_beta(j)) >= 2147483647.0)
-                return fail(c, SNLM_EINVAL, "recursive-Gaussian distances of a pass exceed 2 GiB");
+            if (iir_too_big(n, (int)((long)D * H * W / n), S, iir_beta(j)))
+                return fail(c, SNLM_EINVAL, "recursive-Gaussian buffers of a pass exceed 2 GiB");
         }
     const char* ib = (const char*)img;
     const char* ob = (const char*)out;

@@ -10,16 +10,27 @@
 // forward over v in [-L, n + L) (its three past outputs starting as D(-L)),
 // then by the same recursion backward over w (its three future outputs
 // starting as w(n + L - 1)); sqrt(2 pi) beta times the result at u is the
-// distance between the patches at u and u+s.  One pass runs three kernels
-// (four for lines that are contiguous in memory, which first make a
-// transposed copy of their input with snlm_iir_transpose_kernel and read
-// that instead):
-//   snlm_iir_fwd_kernel   w(v) for v in [-S, n + L), in segments
-//   snlm_iir_bwd_kernel   the distances for u in [-S, n), in segments
-//   snlm_iir_nlm_kernel<S, ROWS>  the 1D NLM of eq. 1dNLM with the weights
-//       exp2(-d) of the stored distances, with the pairing, accumulation
-//       order and pre-chunk of the lifted pass (results do not depend on its
-//       segment length).
+// distance between the patches at u and u+s, and exp2 of minus it the weight
+// of the pair (u, u+s) in eq. 1dNLM.
+//
+// Positions are grouped in blocks of 16: block j holds [16 j, 16 j + 16);
+// blocks -1 .. jhi = (n + L - 1) / 16 cover everything a pass needs.  One pass
+// runs two kernels (three for lines that are contiguous in memory, which
+// first make a transposed copy of their input with snlm_iir_transpose_kernel
+// and read that instead):
+//   snlm_iir_fwd_kernel   the forward recursion of every offset, in
+//       segments; it stores only its state (w'(p-1), w'(p-2), w'(p-3)) in FP64
+//       at the start p = max(16 j, -L) of every block: 24 bytes per 16
+//       samples instead of the 64 of the values themselves.
+//   snlm_iir_nlm_kernel<S>  one workgroup of S waves per (64 lines, segment
+//       of outputs); wave s owns offset s.  It walks the segment's blocks
+//       from the top down: each wave recomputes its block of w from the
+//       stored state (the same operations as the forward kernel, so the same
+//       values), runs the backward recursion over it and writes the block's
+//       weights to LDS; then all waves gather the outputs of the block above,
+//       whose pairs are now all weighted: y(p) = (x(p) + sum_s [w(p, p+s)
+//       x(p+s) + w(p-s, p) x(p-s)]) / (1 + sum_s [w(p, p+s) + w(p-s, p)]).
+//       Neither w nor the distances ever reach memory; one exp per pair.
 // A segment of either recursion starts W samples before its first output
 // (forward) or after its last (backward), from the steady state of the value
 // found there, or at the line's own start where that comes first.  The
@@ -28,16 +39,20 @@
 // recursion far below FP32 resolution.  Segment lengths depend on the job
 // only, never on the device.
 //
-// The recursion's state and coefficients are FP64: for wide kernels the poles
+// Both recursions run on scaled values, w' = w / B forward and y'' = y / B^2
+// backward: w'(v) = D(v) + a1 w'(v-1) + a2 w'(v-2) + a3 w'(v-3), y''(v) =
+// w'(v) + a1 y''(v+1) + ..., the same filter without a multiply by B per step
+// (the steady states become D / B and w' / B, the distance sqrt(2 pi) beta B^2
+// y'').  The state and coefficients are FP64: for wide kernels the poles
 // approach 1 and B ~ 1.6 / (0.42 q^3) is small, so FP32 rounding of the
 // coefficients alone would move the DC gain by ~1e-7 / B (0.2% at beta = 20)
 // and every step's rounding would be amplified up to 1 / B times.  FP64 FMAs
-// issue at the FP32 rate on this chip.  Lifted samples and stored values are
-// FP32.
+// issue at half the FP32 rate on this chip.  Lifted samples, distances and
+// weights are FP32.
 //
-// Buffers (line fastest: every access of a wave is one 256-byte row):
-//   w[((s - 1) * nvw + v + S) * nlines + line],     v in [-S, n + L), nvw = n + L + S
-//   dist[((s - 1) * nvd + u + S) * nlines + line],  u in [-S, n),     nvd = n + S
+// Stored states (line fastest: every access of a wave is one 512-byte row):
+//   ck[(((s - 1) * nblk + j + 1) * 3 + k) * nlines + line],  k = 0, 1, 2 for
+//   w'(p-1), w'(p-2), w'(p-3);  j in [-1, nblk - 2]
 #pragma once
 
 #include "snlm_device.hpp"
@@ -45,62 +60,73 @@
 namespace snlm {
 
 struct IirArgs {
-    PassDesc pass;         // the pass whose distances are wanted (input addressing, n, alpha)
-    float* w;              // forward output
-    float* dist;           // distances
-    uint32_t w_bytes, dist_bytes;
+    PassDesc pass;         // samples in (a row pass: the transposed copy), n, alpha, outputs
+    double* ck;            // forward states at block starts
+    uint32_t ck_bytes;
     int32_t S;             // search half-width (offsets 1..S)
     int32_t L;             // the recursion runs L samples beyond each end of the line
-    int32_t W;             // warm-up of a segment that does not start at the line's start
-    int32_t seg;           // outputs per segment (both recursions)
-    int32_t nseg_f, nseg_b;  // segments per (line, s): forward over [-S, n + L), backward over [-S, n)
+    int32_t W;             // warm-up of a segment that does not start at the line's start (multiple of 16)
+    int32_t nblk;          // blocks per (offset, line): -1 .. nblk - 2
+    int32_t fwd_blocks;    // blocks per forward segment
+    int32_t nseg_f;        // forward segments per (line group, offset)
+    int32_t seg;           // outputs per segment of the NLM kernel (multiple of 16)
     int32_t pad0;
-    double B, a1, a2, a3;  // recursion coefficients (a_k = b_k / b0)
-    double scale;          // sqrt(2 pi) beta: unit gain -> the Gaussian's mass
+    double inv_B, a1, a2, a3;  // 1 / B and the recursion coefficients a_k = b_k / b0
+    double scale;              // sqrt(2 pi) beta B^2: the distance from y''
 };
 
-struct IirNlmArgs {
-    PassDesc pass;        // samples in (a row pass: the transposed copy) and out
-    const float* dist;    // distances written by snlm_iir_bwd_kernel for this pass
-    uint32_t dist_bytes;
-    int32_t nv;           // n + S
-};
+typedef unsigned int iir_u32x2 __attribute__((ext_vector_type(2)));
 
-// Element (s, v) of a w or dist buffer for one lane's line.
-struct DistIO {
+// The stored states of one lane's line: the line's part of the offset goes in
+// the per-lane offset register, the (wave-uniform) offset / block / word part
+// in the scalar one.
+struct CkIO {
     __amdgpu_buffer_rsrc_t r;
-    int32_t base_b;  // line * 4
-    int32_t pos_b;   // nlines * 4
-    int32_t row_b;   // nv * nlines * 4 (one offset s)
-    int32_t S;
+    int32_t base_b;  // line * 8
+    int32_t row_b;   // nlines * 8
+    int32_t nblk;
 
-    // The line's part of the offset goes in the per-lane offset register, the
-    // (wave-uniform) offset and position part in the scalar one.
-    __device__ __forceinline__ int uoff(int s, int u) const { return (s - 1) * row_b + (u + S) * pos_b; }
-    __device__ __forceinline__ float load(int s, int u) const {
-        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, base_b, uoff(s, u), 0));
+    __device__ __forceinline__ int off(int s, int j, int k) const { return (((s - 1) * nblk + j + 1) * 3 + k) * row_b; }
+    __device__ __forceinline__ double load(int s, int j, int k) const {
+        const iir_u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, base_b, off(s, j, k), 0);
+        return __builtin_bit_cast(double, v);
     }
-    __device__ __forceinline__ void store(int s, int u, float v) const {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, base_b, uoff(s, u), 0);
+    // a store that, unless keep, goes past the buffer's extent (its size as
+    // the uniform offset: line * 8 + size stays below 2^32 as both are below
+    // 2^31), where the bounds check drops it
+    __device__ __forceinline__ void store_or_drop(int s, int j, int k, double x, bool keep, uint32_t bytes) const {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(iir_u32x2, x), r, base_b,
+                                              keep ? off(s, j, k) : (int)bytes, 0);
     }
 };
 
-__device__ __forceinline__ DistIO make_dist_io(const float* buf, uint32_t bytes, int line, int nlines, int nv, int S) {
-    DistIO o;
+__device__ __forceinline__ CkIO make_ck_io(const double* buf, uint32_t bytes, int line, int nlines, int nblk) {
+    CkIO o;
     o.r = make_rsrc(buf, bytes);
-    o.base_b = line * 4;
-    o.pos_b = nlines * 4;
-    o.row_b = nv * nlines * 4;
-    o.S = S;
+    o.base_b = line * 8;
+    o.row_b = nlines * 8;
+    o.nblk = nblk;
     return o;
 }
 
-// Workgroup t: group t % ngroups, segment k = (t / ngroups) % nseg, offset
-// s = t / (ngroups * nseg) + 1 (waves of one group and offset run side by
-// side and share the line's samples in L2).
+// One step of the scaled recursion (forward over D, or backward over w'):
+// the newest state word enters last, so only one FMA waits for the previous
+// step.
+__device__ __forceinline__ double iir_step(double a1, double a2, double a3, double in, double w1, double w2,
+                                           double w3) {
+    return __builtin_fma(a1, w1, __builtin_fma(a2, w2, __builtin_fma(a3, w3, in)));
+}
+
+// The lifted input of the forward recursion from two scaled samples.
+__device__ __forceinline__ double iir_lift(float xa, float xb) {
+    const float dd = xa - xb;
+    return (double)(dd * dd);
+}
+
+// Workgroup t of the forward kernel: group t % ngroups, segment k = (t /
+// ngroups) % nseg, offset s = t / (ngroups * nseg) + 1.
 struct IirWave {
     int group, k, s, lane, line, line0;
-    bool active;
 };
 
 __device__ __forceinline__ IirWave iir_wave(const PassDesc& d, int nseg) {
@@ -111,177 +137,345 @@ __device__ __forceinline__ IirWave iir_wave(const PassDesc& d, int nseg) {
     o.s = t / (d.ngroups * nseg) + 1;
     o.lane = threadIdx.x & (kLanes - 1);
     o.line0 = o.group * kLanes;
-    o.active = o.line0 + o.lane < d.nlines;
     o.line = min(o.line0 + o.lane, d.nlines - 1);
     return o;
 }
 
-// Forward recursion of one segment: outputs w(v) for v in [a, b), a = -S + k
-// seg, b = min(a + seg, n + L); the recursion starts at vs = max(a - W, -L)
-// (W a multiple of 16, so away from the line's start every 16-step block is
-// either all warm-up or all output).  Each lane streams its line's scaled
-// samples through NPF register buffers (16 samples each, issued NPF chunks
-// ahead) into an LDS ring of two chunks: chunk c (positions vs + 16c ..)
-// lands in slots (16c mod 32) .. + 15, and the chunk in slots 0..15 is also
-// copied to slots 32..47, so a block's 16 + s <= 32 samples sit at
-// consecutive slots.  A block at v0 reads chunks v0 and v0 + 16; the chunk at
-// v0 + 32 replaces chunk v0 once the block is done.
+// Forward recursion of one segment, blocks [ja, jb) with ja = -1 + k
+// fwd_blocks: stores the state at the start of each of them.  The recursion
+// starts at vs = max(16 ja - W, -L) and runs in steps of 16 from g0 = vs
+// rounded down to a multiple of 16 (positions below vs are skipped), so that
+// every group of 16 steps begins at a block start.  Each lane streams its
+// line's samples through NPF register buffers (16 samples each, issued NPF
+// chunks ahead) into an LDS ring of two chunks: chunk c (positions g0 + 16c
+// ..) lands in slots (16c mod 32) .. + 15, and the chunk in slots 0..15 is
+// also copied to slots 32..47, so a group's 16 + s <= 32 samples sit at
+// consecutive slots.  A group at v0 reads chunks v0 and v0 + 16; the chunk at
+// v0 + 32 replaces chunk v0 once the group is done.  Every load takes the
+// same path (a reflected position is just another offset, FP16 a template
+// parameter), so the compiler counts the loads in flight and waits for the
+// oldest chunk only.
 // Lanes past the last line repeat the last line's work and store its values
 // to its addresses (the same bits), so no store needs a lane mask.
-template <int NPF>
+template <int NPF, bool F16>
 __global__ __launch_bounds__(kLanes) void snlm_iir_fwd_kernel(IirArgs a) {
     constexpr int C = kChunk;
     constexpr int RING = 32;  // slots of distinct positions: [v0, v0 + 32) in use
-    static_assert(NPF >= 3, "two chunks are taken before the first step, the third in the loop");
+    static_assert(NPF >= 3 && NPF * C <= 64, "two chunks are taken before the first step; <= 63 loads in flight");
     __shared__ float ring[(RING + C) * kLanes];  // ring[slot * 64 + lane]
     const PassDesc& d = a.pass;
     const IirWave wv = iir_wave(d, a.nseg_f);
     const int s = wv.s, lane = wv.lane;
     const LineIO io = make_io<false>(d, wv.line0, lane, nullptr);
-    const DistIO wio = make_dist_io(a.w, a.w_bytes, wv.line, d.nlines, d.n + a.L + a.S, a.S);
+    const CkIO ck = make_ck_io(a.ck, a.ck_bytes, wv.line, d.nlines, a.nblk);
     const float alpha = d.alpha;
-    const double B = a.B, a1 = a.a1, a2 = a.a2, a3 = a.a3;
-    const int L = a.L, n = d.n;
-    const int out_a = -a.S + wv.k * a.seg;
-    const int out_b = min(out_a + a.seg, n + L);
-    const int vs = max(out_a - a.W, -L);
+    const double a1 = a.a1, a2 = a.a2, a3 = a.a3;
+    const int n = d.n;
+    const int ja = -1 + wv.k * a.fwd_blocks;
+    const int jb = min(ja + a.fwd_blocks, a.nblk - 1);
+    const int vs = max(C * ja - a.W, -a.L);
+    const int g0 = vs & ~(C - 1);
 
-    // 16 samples from position p: plain offsets inside the line, reflected
-    // ones near its ends
-    auto load16 = [&](int p, float* v) {
-        if (p >= 0 && p + C <= n && !io.f16) {
-            const int base = p * io.in_pos_b;
-#pragma unroll
-            for (int t = 0; t < C; ++t)
-                v[t] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(io.rin, io.in_base_b,
-                                                                                     base + t * io.in_pos_b, 0));
-        } else {
-            io.template load<C>(p, v);
-        }
-    };
-    float vb[NPF][C];
-    int issued = vs;  // next position to load
-    int taken = vs;   // positions below this are in the ring
-#pragma unroll
-    for (int q = 0; q < NPF; ++q) {
-        load16(issued, vb[q]);
-        issued += C;
-    }
-    auto take = [&](int q) {
-        const int slot = (taken - vs) & (RING - 1);
-#pragma unroll
-        for (int t = 0; t < C; ++t) ring[(slot + t) * kLanes + lane] = alpha * vb[q][t];
-        if (slot == 0) {
-#pragma unroll
-            for (int t = 0; t < C; ++t) ring[(RING + t) * kLanes + lane] = alpha * vb[q][t];
-        }
-        taken += C;
-        load16(issued, vb[q]);
-        issued += C;
-    };
-    take(0);
-    take(1);  // chunks vs and vs + 16
-    int v0 = vs;
-    const float dd0 = ring[lane] - ring[s * kLanes + lane];
-    double w1 = (double)(dd0 * dd0), w2 = w1, w3 = w1;
-    auto fwd16 = [&]() {
-        const int b = (v0 - vs) & (RING - 1);  // 0 or 16
-        const float* rx = ring + b * kLanes + lane;
-        const float* ry = rx + s * kLanes;
-        const bool all_out = v0 >= out_a && v0 + C <= out_b;
-        const bool none_out = v0 + C <= out_a || v0 >= out_b;
-        const int off0 = wio.uoff(s, v0);
+    // the raw bits of 16 samples from position p (reflected near the ends)
+    auto load16 = [&](int p, unsigned* v) {
 #pragma unroll
         for (int t = 0; t < C; ++t) {
-            const float dd = rx[t * kLanes] - ry[t * kLanes];
-            const double w = __builtin_fma(a1, w1, __builtin_fma(a2, w2, __builtin_fma(a3, w3, B * (double)(dd * dd))));
+            const int pt = p + t;
+            const int so = ((unsigned)pt < (unsigned)n ? pt : refl(pt, n)) * io.in_pos_b;
+            if constexpr (F16)
+                v[t] = __builtin_amdgcn_raw_buffer_load_b16(io.rin, io.in_base_b, so, 0);
+            else
+                v[t] = __builtin_amdgcn_raw_buffer_load_b32(io.rin, io.in_base_b, so, 0);
+        }
+    };
+    auto sample = [&](unsigned bits) {
+        if constexpr (F16)
+            return (float)__builtin_bit_cast(_Float16, (unsigned short)bits);
+        else
+            return __builtin_bit_cast(float, bits);
+    };
+    unsigned vb[NPF][C];
+#pragma unroll
+    for (int q = 0; q < NPF; ++q) load16(g0 + C * q, vb[q]);
+    // chunk c (positions g0 + 16 c ..) from buffer c mod NPF into ring slots
+    // 16 c mod 32, then that buffer loads chunk c + NPF
+    auto take = [&](int c, int q) {
+        const int slot = (C * c) & (RING - 1);
+#pragma unroll
+        for (int t = 0; t < C; ++t) ring[(slot + t) * kLanes + lane] = alpha * sample(vb[q][t]);
+        if (slot == 0) {
+#pragma unroll
+            for (int t = 0; t < C; ++t) ring[(RING + t) * kLanes + lane] = alpha * sample(vb[q][t]);
+        }
+        load16(g0 + C * (c + NPF), vb[q]);
+    };
+    take(0, 0);
+    take(1, 1);
+    const int i0 = vs - g0;
+    const double d0 = iir_lift(ring[i0 * kLanes + lane], ring[(i0 + s) * kLanes + lane]) * a.inv_B;
+    double w1 = d0, w2 = d0, w3 = d0;  // the steady state of D(vs)
+    // group i (positions g0 + 16 i ..) reads ring slots 16 i mod 32 ..
+    auto fwd16 = [&](int i, int skip) {
+        const float* rx = ring + ((C * i) & (RING - 1)) * kLanes + lane;
+        const float* ry = rx + s * kLanes;
+#pragma unroll
+        for (int t = 0; t < C; ++t) {
+            if (t < skip) continue;
+            const double w = iir_step(a1, a2, a3, iir_lift(rx[t * kLanes], ry[t * kLanes]), w1, w2, w3);
             w3 = w2;
             w2 = w1;
             w1 = w;
-            if (all_out || (!none_out && v0 + t >= out_a && v0 + t < out_b))
-                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, (float)w), wio.r, wio.base_b,
-                                                      off0 + t * wio.pos_b, 0);
         }
-        v0 += C;
     };
-    while (v0 < out_b) {
+    // the state at the start of group i, block j = g0 / 16 + i, when it is
+    // one of the segment's (the others go past the buffer, where the bounds
+    // check drops them: every group issues the same memory operations)
+    const int jg0 = g0 >> 4;
+    auto store_state = [&](int i) {
+        const int j = jg0 + i;
+        const bool mine = j >= ja && j < jb;
+        const int jc = min(max(j, ja), jb - 1);  // an in-range block for the offset arithmetic
+        ck.store_or_drop(s, jc, 0, w1, mine, a.ck_bytes);
+        ck.store_or_drop(s, jc, 1, w2, mine, a.ck_bytes);
+        ck.store_or_drop(s, jc, 2, w3, mine, a.ck_bytes);
+    };
+    // group 0 (its first vs - g0 positions are before the recursion's start)
+    store_state(0);
+    const int m = jb - jg0;  // group starts whose state the segment stores: 0 .. m - 1
+    if (m > 1) {
+        fwd16(0, vs - g0);
+        take(2, 2 % NPF);
+        // groups 1 .. NPF * iters in whole runs of NPF (the host sizes
+        // segments so that only a line's first and last segment run past
+        // m - 1, computing a few groups nobody stores)
+        const int iters = (m - 2) / NPF + 1;
+        for (int it = 0; it < iters; ++it) {
 #pragma unroll
-        for (int q = 0; q < NPF; ++q) {
-            if (v0 < out_b) {
-                fwd16();
-                // buffers are taken in issue order: 2, 3, .., NPF-1, 0, 1, 2, ...
-                take((q + 2) % NPF);  // the chunk at the new v0 + 16
+            for (int q = 0; q < NPF; ++q) {
+                const int i = 1 + NPF * it + q;
+                store_state(i);
+                fwd16(1 + q, 0);  // ring slots depend on the parity of i only
+                take(i + 2, (q + 3) % NPF);
             }
         }
     }
 }
 
-// Backward recursion of one segment: distances for u in [a, b), a = -S + k
-// seg, b = min(a + seg, n); the recursion starts at min(b - 1 + W, n + L - 1)
-// and reads w back C positions at a time through NB register buffers, so
-// that NB - 1 chunks stay in flight while one is filtered (the kernel is
-// bound by the bytes in flight: its grid gives only a few waves per SIMD).
-// Stores as in the forward kernel (no lane masks).
-template <int C>
-__global__ __launch_bounds__(kLanes) void snlm_iir_bwd_kernel(IirArgs a) {
-    constexpr int NB = 4;
+// LDS of the NLM kernel: the sample ring (96 slots of 64 lanes: positions
+// mod 64, slots 64..95 repeating 0..31) and the weights of S offsets for two
+// blocks (positions mod 32).
+constexpr int kIirXSlots = 96;
+template <int S>
+constexpr int iir_nlm_lds_bytes() {
+    return (kIirXSlots + S * 2 * kChunk) * kLanes * 4;
+}
+
+// Workgroup t: group t % ngroups, segment t / ngroups of seg outputs [a0, b0).
+// Wave q owns offset s = q + 1.  Blocks jbot = a0 / 16 - 1 (weights of the
+// pairs that reach into the segment from below) .. jw = (b0 - 1) / 16 carry
+// weights; the backward recursion starts at vtop = min(16 (jw + 1) + W - 1,
+// n + L - 1), W samples above the segment's top block (or at the line's
+// end), so the blocks up to jt = vtop / 16 are its warm-up.  Step j (from jt
+// down to jbot):
+//   1. the stored state of block j - 1 starts loading; the samples of block
+//      j - 1 (loaded during the previous step, positions t = q, q + S, .. of
+//      the block by wave q) go into the ring, and those of block j - 2 start
+//      loading;
+//   2. each wave recomputes w' over block j from its stored state, then runs
+//      the backward recursion down the block and (j <= jw) writes the weights
+//      exp2(-sqrt(2 pi) beta B^2 y'') of its offset to LDS;
+//   3. barrier; the waves gather the outputs of block j + 1 (when it lies in
+//      the segment): positions t = q, q + S, .. of the block go to wave q;
+//   4. barrier (the next step overwrites the weights of block j + 1 and the
+//      samples of block j + 3).
+// Step j reads samples of blocks j .. j + 2 (positions up to 16 j + 47 from
+// ring slot 16 j mod 64, hence the 32 repeated slots) and weights of blocks
+// j and j + 1.  Every wave runs the same steps, so the barriers match.
+template <int S>
+__global__ __launch_bounds__(kLanes* S) void snlm_iir_nlm_kernel(IirArgs a) {
+    constexpr int C = kChunk;
+    constexpr int NR = (C + S - 1) / S;  // ring positions per wave and block
+    static_assert(S >= 1 && S <= kMaxS, "parameter range");
+    __shared__ float xr[kIirXSlots * kLanes];     // a x(v) at slot (v mod 64) * 64 + lane
+    __shared__ float wt[S * 2 * C * kLanes];      // w(u, u+s) at ((s - 1) * 32 + u mod 32) * 64 + lane
     const PassDesc& d = a.pass;
-    const IirWave wv = iir_wave(d, a.nseg_b);
-    const int s = wv.s;
-    const int S = a.S;
-    const DistIO wio = make_dist_io(a.w, a.w_bytes, wv.line, d.nlines, d.n + a.L + S, S);
-    const DistIO dio = make_dist_io(a.dist, a.dist_bytes, wv.line, d.nlines, d.n + S, S);
-    const double B = a.B, a1 = a.a1, a2 = a.a2, a3 = a.a3;
-    const double scale = a.scale;
-    const int out_a = -S + wv.k * a.seg;
-    const int out_b = min(out_a + a.seg, d.n);
-    const int vtop = min(out_b - 1 + a.W, d.n + a.L - 1);
-    double y1 = (double)wio.load(s, vtop), y2 = y1, y3 = y1;
-    // w at top, top - 1, .., top - C + 1 (positions below out_a, never used,
-    // read out_a's).  No branches around the loads or the stores below: the
-    // compiler then counts them and waits only for the chunk it filters.
-    auto load16 = [&](int top, float* dst) {
+    const int group = blockIdx.x % d.ngroups;
+    const int kseg = blockIdx.x / d.ngroups;
+    const int q = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int s = q + 1;
+    const int line0 = group * kLanes;
+    const int line = min(line0 + lane, d.nlines - 1);
+    const LineIO io = make_io<false>(d, line0, lane, nullptr);
+    const CkIO ck = make_ck_io(a.ck, a.ck_bytes, line, d.nlines, a.nblk);
+    const float alpha = d.alpha, inv_alpha = d.inv_alpha;
+    const double a1 = a.a1, a2 = a.a2, a3 = a.a3, scale = a.scale;
+    const int n = d.n, L = a.L;
+    const int a0 = kseg * a.seg;
+    const int b0 = min(a0 + a.seg, n);
+    const int jw = (b0 - 1) >> 4;
+    const int jbot = (a0 >> 4) - 1;
+    const int vtop = min(C * (jw + 1) + a.W - 1, n + L - 1);
+    const int jt = vtop >> 4;
+
+    // this wave's share of a block's samples: positions q + S r, kept as the
+    // loaded bits (FP16 samples convert when they enter the ring, so no load
+    // is waited for before then)
+    unsigned xn[NR];
+    auto load_part = [&](int j) {
 #pragma unroll
-        for (int t = 0; t < C; ++t) dst[t] = wio.load(s, max(top - t, out_a));
+        for (int r = 0; r < NR; ++r) {
+            const int p = C * j + q + S * r;
+            if (q + S * r < C) {
+                int vo = io.in_base_b, so = p * io.in_pos_b;
+                if (p < 0 || p >= n) {
+                    vo += refl(p, n) * io.in_pos_b;
+                    so = 0;
+                }
+                xn[r] = io.f16 ? (unsigned)__builtin_amdgcn_raw_buffer_load_b16(io.rin, vo, so, 0)
+                               : __builtin_amdgcn_raw_buffer_load_b32(io.rin, vo, so, 0);
+            }
+        }
     };
-    float buf[NB][C];
+    auto put_part = [&](int j) {
+        const int slot = (C * j) & 63;
 #pragma unroll
-    for (int q = 0; q < NB; ++q) load16(vtop - q * C, buf[q]);
-    int top = vtop;
-    bool more = true;
-    while (more) {
-#pragma unroll
-        for (int q = 0; q < NB; ++q) {
-            if (!more) break;
-            const int off0 = dio.uoff(s, top);
+        for (int r = 0; r < NR; ++r) {
+            const int t = q + S * r;
+            if (t < C) {
+                const float x = io.f16 ? (float)__builtin_bit_cast(_Float16, (unsigned short)xn[r])
+                                       : __builtin_bit_cast(float, xn[r]);
+                xr[(slot + t) * kLanes + lane] = alpha * x;
+                if (slot < 32) xr[(64 + slot + t) * kLanes + lane] = alpha * x;
+            }
+        }
+    };
+    load_part(jt + 1);
+    put_part(jt + 1);
+    load_part(jt);
+    put_part(jt);
+    load_part(jt - 1);
+    double c0 = ck.load(s, jt, 0), c1 = ck.load(s, jt, 1), c2 = ck.load(s, jt, 2);
+    double y1 = 0.0, y2 = 0.0, y3 = 0.0;  // backward state
+    float* wq = wt + (q * 2 * C) * kLanes + lane;
+    __syncthreads();
+
+    for (int j = jt; j >= jbot; --j) {
+        const int base = C * j;
+        const int t_lo = max(0, -L - base);
+        const int t_hi = min(C - 1, vtop - base);
+        const bool full = t_lo == 0 && t_hi == C - 1;
+        const int xb = base & 63;  // ring slot of position base
+        float* wblk = wq + (base & 31) * kLanes;  // this offset's weight of position base
+        // ---- 1. state and samples in flight
+        double w1 = c0, w2 = c1, w3 = c2;
+        if (j > jbot) {
+            c0 = ck.load(s, j - 1, 0);
+            c1 = ck.load(s, j - 1, 1);
+            c2 = ck.load(s, j - 1, 2);
+            put_part(j - 1);  // its slots held block j + 3, last read by the previous step's gather
+            if (j - 1 > jbot) load_part(j - 2);
+        }
+        // ---- 2. w' over the block, then backward
+        const float* rx = xr + xb * kLanes + lane;  // a x(base + t) at rx[t * 64]
+        const float* ry = rx + s * kLanes;          // a x(base + t + s)
+        double wv[C];
+        if (full) {
 #pragma unroll
             for (int t = 0; t < C; ++t) {
-                const double y =
-                    __builtin_fma(a1, y1, __builtin_fma(a2, y2, __builtin_fma(a3, y3, B * (double)buf[q][t])));
+                const double w = iir_step(a1, a2, a3, iir_lift(rx[t * kLanes], ry[t * kLanes]), w1, w2, w3);
+                w3 = w2;
+                w2 = w1;
+                w1 = w;
+                wv[t] = w;
+            }
+            if (j == jt) y1 = y2 = y3 = wv[C - 1] * a.inv_B;  // the steady state of w'(vtop)
+            if (j <= jw) {
+#pragma unroll
+                for (int t = C - 1; t >= 0; --t) {
+                    const double y = iir_step(a1, a2, a3, wv[t], y1, y2, y3);
+                    y3 = y2;
+                    y2 = y1;
+                    y1 = y;
+                    wblk[t * kLanes] = __builtin_amdgcn_exp2f(-(float)(scale * y));
+                }
+            } else {
+#pragma unroll
+                for (int t = C - 1; t >= 0; --t) {
+                    const double y = iir_step(a1, a2, a3, wv[t], y1, y2, y3);
+                    y3 = y2;
+                    y2 = y1;
+                    y1 = y;
+                }
+            }
+        } else {
+            // a block cut by the line's run-in or by the recursion's start
+#pragma unroll
+            for (int t = 0; t < C; ++t) {
+                wv[t] = 0.0;
+                if (t < t_lo || t > t_hi) continue;
+                const double w = iir_step(a1, a2, a3, iir_lift(rx[t * kLanes], ry[t * kLanes]), w1, w2, w3);
+                w3 = w2;
+                w2 = w1;
+                w1 = w;
+                wv[t] = w;
+            }
+#pragma unroll
+            for (int t = C - 1; t >= 0; --t) {
+                if (t < t_lo || t > t_hi) continue;
+                if (j == jt && t == t_hi) y1 = y2 = y3 = wv[t] * a.inv_B;
+                const double y = iir_step(a1, a2, a3, wv[t], y1, y2, y3);
                 y3 = y2;
                 y2 = y1;
                 y1 = y;
-                // positions outside [out_a, out_b) go past the buffer's
-                // extent (its size as the uniform offset: line * 4 + size
-                // stays below 2^32 as both are below 2^31), where the bounds
-                // check drops the store
-                const int so = (top - t >= out_a && top - t < out_b) ? off0 - t * dio.pos_b : (int)a.dist_bytes;
-                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, (float)(scale * y)), dio.r,
-                                                      dio.base_b, so, 0);
+                if (j <= jw) wblk[t * kLanes] = __builtin_amdgcn_exp2f(-(float)(scale * y));
             }
-            more = top - C >= out_a;
-            if (more) load16(top - NB * C, buf[q]);  // the chunk NB positions on
-            top -= C;
         }
+        __syncthreads();
+        // ---- 3. outputs of block j + 1: this wave's positions together (a
+        // position past the block's end repeats its last one, unstored), so
+        // their LDS reads overlap
+        if (j + 1 <= jw) {
+            const float* xg = xr + (xb + C) * kLanes + lane;  // a x(16 (j + 1) + t) at xg[t * 64]
+            float P[NR], Q[NR];
+            int tt[NR];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                tt[r] = min(q + S * r, C - 1);
+                P[r] = xg[tt[r] * kLanes];
+                Q[r] = 1.0f;
+            }
+#pragma unroll
+            for (int o = 1; o <= S; ++o) {
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    const int p = base + C + tt[r];
+                    const float* xp = xg + tt[r] * kLanes;
+                    const float wr = wt[((o - 1) * 2 * C + (p & 31)) * kLanes + lane];        // pair (p, p + o)
+                    const float wl = wt[((o - 1) * 2 * C + ((p - o) & 31)) * kLanes + lane];  // pair (p - o, p)
+                    P[r] = __builtin_fmaf(wr, xp[o * kLanes], P[r]);
+                    P[r] = __builtin_fmaf(wl, xp[-o * kLanes], P[r]);
+                    Q[r] += wr;
+                    Q[r] += wl;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const int t = q + S * r;
+                const int p = base + C + t;
+                if (t < C && p < b0) io.store(p, (P[r] * __builtin_amdgcn_rcpf(Q[r])) * inv_alpha);
+            }
+        }
+        __syncthreads();
     }
 }
 
-// Transposed FP32 copy of a pass's input for the forward recursion of a pass
-// whose lines are contiguous in memory: xt[p * nlines + line] = x(line, p).
-// Reading lines across lanes touches one cache line per lane and sample; the
-// copy lets every offset's forward wave read 64 lines' sample p as one
-// 256-byte row.  Workgroup (four waves): 64 lines x 64 positions through an
-// LDS tile (odd row stride: no bank conflicts either way).
+// Transposed FP32 copy of a pass's input for the recursions of a pass whose
+// lines are contiguous in memory: xt[p * nlines + line] = x(line, p).  Reading
+// lines across lanes touches one cache line per lane and sample; the copy
+// lets every wave read 64 lines' sample p as one 256-byte row.  Workgroup
+// (four waves): 64 lines x 64 positions through an LDS tile (odd row stride:
+// no bank conflicts either way).
 struct IirTransposeArgs {
     PassDesc pass;
     float* xt;
@@ -326,112 +520,6 @@ __global__ __launch_bounds__(4 * kLanes) void snlm_iir_transpose_kernel(IirTrans
             __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, tile[lane * (kLanes + 1) + i]), r,
                                                   ((p0 + i) * d.nlines + line) * 4, 0, 0);
     }
-}
-
-// Samples [seg_a, seg_b) of one line from stored distances (seg_a a multiple
-// of kChunk).  As run_segment with K = 0 for the samples: the window holds
-// positions c0 .. c0 + C + S - 1, and pair (u, u+s) takes d = dist(s, u).
-template <int S>
-__device__ __forceinline__ void run_segment_dist(const PassDesc& d, const LineIO& io, const DistIO& dio,
-                                                 int seg_a, int seg_b) {
-    constexpr int C = kChunk;
-    constexpr int NX = C + S;
-    constexpr int NP = C + S;
-    static_assert(S >= 1 && S <= kMaxS, "parameter range");
-    const float alpha = d.alpha;
-    const float inv_alpha = d.inv_alpha;
-    const int nlast = d.n - 1;
-    float xs[NX], P[NP], Q[NP], nx[C];
-
-    int c0 = seg_a - C;
-    io.template load<NX>(c0, xs);
-#pragma unroll
-    for (int j = 0; j < NX; ++j) xs[j] = alpha * xs[j];
-#pragma unroll
-    for (int i = 0; i < NP; ++i) {
-        P[i] = xs[i];
-        Q[i] = 1.0f;
-    }
-    io.issue_chunk(seg_a + S, nx);
-
-    // ---- pre-chunk: pairs (u, u+s) with u in [seg_a - s, seg_a) ----
-#pragma unroll
-    for (int s = 1; s <= S; ++s) {
-        __builtin_amdgcn_sched_barrier(0);
-        float r[C];
-#pragma unroll
-        for (int i = C - s; i < C; ++i) r[i] = dio.load(s, c0 + i);
-#pragma unroll
-        for (int i = C - s; i < C; ++i)
-            accumulate_pair<0>(xs, P, Q, i, s, __builtin_amdgcn_exp2f(-r[i]), false);
-    }
-
-    // distances of offset s for the chunk at c: positions past the line's end
-    // (pairs whose both centres are past it) read the last stored one
-    auto row = [&](int s, int c, float* dst) {
-#pragma unroll
-        for (int i = 0; i < C; ++i) dst[i] = dio.load(s, min(c + i, nlast));
-    };
-    float rc[C], rn[C];
-    row(1, seg_a, rc);
-    bool staged_store_last = false;  // the previous chunk ended with 4 tile stores
-    for (c0 = seg_a;; c0 += C) {
-        io.finish_chunk(c0 + S, nx, staged_store_last);
-        advance_chunk<S, 0>(xs, P, Q, nx, alpha);
-        const bool has_next = c0 + C < seg_b;
-        if (has_next) io.issue_chunk(c0 + C + S, nx);
-#pragma unroll
-        for (int s = 1; s <= S; ++s) {
-            // one offset at a time (bounds the loads in flight, and so the
-            // registers); the next offset's distances (or the next chunk's
-            // first) load while this offset's pairs are accumulated
-            __builtin_amdgcn_sched_barrier(0);
-            if (s < S)
-                row(s + 1, c0, rn);
-            else if (has_next)
-                row(1, c0 + C, rn);
-            // (the distance as stored: a recursive-filter value can be
-            // slightly negative, and is not clamped)
-#pragma unroll
-            for (int i = 0; i < C; ++i) accumulate_pair<0>(xs, P, Q, i, s, __builtin_amdgcn_exp2f(-rc[i]), true);
-            if (s < S || has_next) {
-#pragma unroll
-                for (int i = 0; i < C; ++i) rc[i] = rn[i];
-            }
-            // Complete this offset's sums here: otherwise the compiler sinks
-            // every offset's arithmetic below the last loads and keeps all
-            // S * 16 distances live at once.
-#pragma unroll
-            for (int i = 0; i + 3 < NP; i += 4)
-                asm volatile("" ::"v"(P[i]), "v"(P[i + 1]), "v"(P[i + 2]), "v"(P[i + 3]), "v"(Q[i]), "v"(Q[i + 1]),
-                             "v"(Q[i + 2]), "v"(Q[i + 3]));
-        }
-        float y[C];
-        normalise(P, Q, inv_alpha, y);
-        staged_store_last = io.store_chunk(c0, seg_b, y);
-        if (!has_next) break;
-    }
-}
-
-// Grid: ngroups * nseg workgroups of one wave, as the direct lifted pass.
-// ROWS: the variant for lines contiguous in memory (the LDS transpose tile for
-// the outputs, as the lifted pass's row variant; its samples come from the
-// transposed copy, which every lane reads coalesced, so the input tile stays
-// unused).
-template <int S, bool ROWS>
-__global__ __launch_bounds__(kLanes) void snlm_iir_nlm_kernel(IirNlmArgs a) {
-    __shared__ __attribute__((aligned(16))) float tiles[ROWS ? kTileIn + kTileOut : 1];
-    const PassDesc& d = a.pass;
-    const int t = blockIdx.x;
-    const int group = t % d.ngroups;
-    const int seg_a = (t / d.ngroups) * d.seg_len;
-    const int seg_b = min(seg_a + d.seg_len, d.n);
-    const int lane = threadIdx.x & (kLanes - 1);
-    const int line0 = group * kLanes;
-    const LineIO io = make_io<ROWS>(d, line0, lane, tiles);
-    const int line = min(line0 + lane, d.nlines - 1);
-    const DistIO dio = make_dist_io(a.dist, a.dist_bytes, line, d.nlines, a.nv, S);
-    run_segment_dist<S>(d, io, dio, seg_a, seg_b);
 }
 
 }  // namespace snlm

@@ -105,12 +105,19 @@ def test_recursive_gaussian_rules():
     for kw in (dict(beta=0.49), dict(beta=256.5), dict(K=0)):
         rc, why = ok(**kw)
         assert rc == snlm.EINVAL and "0.5 <= beta" in why, kw
-    # S (n + L + S) distances per line, L = ceil(6 beta) + S + 3: a 16000 x
-    # 16000 image at S = 16 needs 16 GiB of them
+    # a pass stores 3 S ((n + L - 1) / 16 + 2) FP64 forward states per line,
+    # L = ceil(6 beta) + S + 3: a 16000 x 16000 image at S = 16 needs 6 GiB
     big = dict(img=0x100000, out=0x100000 + 2 * 16000 * 16000 * 4, H=16000, W=16000, S=16, beta=8.0)
     rc, why = ok(**big)
     assert rc == snlm.EINVAL and "2 GiB" in why
     assert snlm.validate(job(**dict(big, kernel="gauss", K=8)))[0] == snlm.OK
+    # at S = 16, beta = 2 the largest square image is 9430 x 9430 (2.147e9
+    # bytes of states, just below 2^31 - 1)
+    for n, want in ((9430, snlm.OK), (9440, snlm.EINVAL)):
+        states = 3 * 16 * ((n + 31 - 1) // 16 + 2) * n * 8
+        assert (states < 2 ** 31 - 1) == (want == snlm.OK)
+        edge = dict(img=0x100000, out=0x100000 + 2 * n * n * 4, H=n, W=n, S=16, beta=2.0)
+        assert ok(**edge)[0] == want, n
 
 
 def test_unknown_enums_rejected():

@@ -81,6 +81,9 @@ def test_iir_recursion_in_segments(W, beta):
 
 
 def test_iir_segment_length_keeps_bits():
+    """The job's seg_len does not reach the recursive kernel: its segments
+    are a function of the image shape, S and beta alone, so any seg_len gives
+    the same bits."""
     import torch
     ctx = _ctx()
     x = torch.from_numpy(_noisy(70, 333, 20.0, 10)).to("cuda:0")
@@ -185,19 +188,27 @@ def test_iir_extremes():
 
 
 def test_iir_largest_buffers():
-    """A 5700 x 5700 image at S = 16, beta = 2: each pass keeps 16 (n + L + 16)
-    forward values per line (2.10 GB, just under the 2 GiB limit of a
-    region) and 16 (n + 16) distances, so the recursions' 32-bit buffer
-    offsets, and the stores the backward pass drops past the distances'
-    end, run near their limit.  The whole output against the oracle."""
+    """A 9430 x 9430 image at S = 16, beta = 2: each pass stores the forward
+    recursion's FP64 state at the start of every block of 16 positions,
+    16 * 593 blocks * 3 words per line (2.147 GB, 0.99997 of the 2 GiB limit
+    of a region), so the 32-bit offsets of those loads and stores run at
+    their limit; one pixel more per side and the job is rejected.  The whole
+    output against the oracle."""
     import torch
-    n = 5700
+    import paper_1407_2343_amd as snlm
+    n = 9430
     L = 12 + 16 + 3
-    assert 0.97 * 2 ** 31 < 16 * (n + L + 16) * n * 4 < 2 ** 31 - 1
-    rng = np.random.default_rng(5700)
+    nblk = (n + L - 1) // 16 + 2
+    assert 0.9999 * 2 ** 31 < 16 * nblk * 3 * 8 * n < 2 ** 31 - 1
+    nb = n + 10
+    assert 16 * ((nb + L - 1) // 16 + 2) * 3 * 8 * nb > 2 ** 31 - 1
+    rng = np.random.default_rng(9430)
     img = (128.0 + 30.0 * rng.standard_normal((n, n))).astype(np.float32)
-    ctx = _ctx(1 << 28)
+    ctx = _ctx(snlm.workspace_bytes(n, n) + (1 << 20))
     _check(ctx, img, 16, 2.0, 300.0)
+    with pytest.raises(snlm.SnlmError) as e:
+        ctx.denoise(torch.zeros((nb, nb), device="cuda:0"), 16, 0, 300.0, "gauss_iir", beta=2.0)
+    assert e.value.status == snlm.EINVAL
     ctx.close()
 
 
