@@ -756,6 +756,28 @@ int iir_nlm_seg(int n, int ngroups, int S, int W) {
     return best_seg;
 }
 
+// Blocks per segment of the forward kernel (workgroups of S waves sharing a
+// 20 KB sample ring): the segment count that minimises (rounds of resident
+// workgroups) x (blocks each walks: its own and the W / 16 of warm-up), with
+// resident workgroups counted for 256 compute units at up to 20 waves each.
+// A function of the job alone.
+int iir_fwd_blocks(int nblk, int ngroups, int S, int W) {
+    const long slots = 256L * std::max(1, std::min(8, 20 / S));
+    long best = -1;
+    int best_blocks = nblk;
+    for (int nseg = 1; nseg <= nblk; ++nseg) {
+        const int per = (nblk + nseg - 1) / nseg;
+        const int used = (nblk + per - 1) / per;
+        const long rounds = ((long)ngroups * used + slots - 1) / slots;
+        const long cost = rounds * (per + W / kChunk);
+        if (best < 0 || cost < best) {
+            best = cost;
+            best_blocks = per;
+        }
+    }
+    return best_blocks;
+}
+
 int iir_pass(snlm_ctx* c, const snlm_job& j, const PassDesc& d, bool rows, hipStream_t st) {
     const double beta = iir_beta(j);
     snlm::IirArgs ia;
@@ -771,14 +793,7 @@ int iir_pass(snlm_ctx* c, const snlm_job& j, const PassDesc& d, bool rows, hipSt
     ia.scale = std::sqrt(2.0 * M_PI) * beta * B * B;
     ia.W = (iir_warmup(ia.a1, ia.a2, ia.a3) + kChunk - 1) / kChunk * kChunk;  // whole blocks
     ia.nblk = iir_blocks(d.n, j.S, beta);
-    // Forward segments: about 2048 waves (two per SIMD: each wave is a serial
-    // chain; more segments cost more warm-up), but at least 2W long; a
-    // segment with warm-up walks fwd_blocks + W / 16 block starts, one then
-    // whole runs of 4 (the kernel's unrolled loop), so fwd_blocks + W / 16 - 1
-    // is made a multiple of 4.
-    const int per_line = std::max(1, (2048 + d.ngroups * j.S - 1) / (d.ngroups * j.S));
-    ia.fwd_blocks = std::max(2 * ia.W / kChunk, (ia.nblk + per_line - 1) / per_line);
-    ia.fwd_blocks += (4 - (ia.fwd_blocks + ia.W / kChunk - 1) % 4) % 4;
+    ia.fwd_blocks = iir_fwd_blocks(ia.nblk, d.ngroups, j.S, ia.W);
     ia.nseg_f = (ia.nblk + ia.fwd_blocks - 1) / ia.fwd_blocks;
     ia.seg = iir_nlm_seg(d.n, d.ngroups, j.S, ia.W);
     const int nseg = (d.n + ia.seg - 1) / ia.seg;
@@ -818,10 +833,9 @@ int iir_pass(snlm_ctx* c, const snlm_job& j, const PassDesc& d, bool rows, hipSt
         t.split = 0;
     }
     void* args[] = {&ia};
-    const void* fwd = ia.pass.in_f16 ? (const void*)&snlm::snlm_iir_fwd_kernel<4, true>
-                                     : (const void*)&snlm::snlm_iir_fwd_kernel<4, false>;
-    HIP_CHECK(c, hipLaunchKernel(fwd, dim3(d.ngroups * j.S * ia.nseg_f), dim3(snlm::kLanes), args, 0, st));
     init_registry();
+    HIP_CHECK(c, hipLaunchKernel(g_reg.iir_fwd[j.S][ia.pass.in_f16 ? 1 : 0], dim3(d.ngroups * ia.nseg_f),
+                                 dim3(snlm::kLanes * j.S), args, 0, st));
     HIP_CHECK(c, hipLaunchKernel(g_reg.iir[j.S], dim3(d.ngroups * nseg), dim3(snlm::kLanes * j.S), args, 0, st));
     if (c->timing) {
         HIP_CHECK(c, hipEventRecord(ev.second, st));

@@ -18,9 +18,10 @@
 // runs two kernels (three for lines that are contiguous in memory, which
 // first make a transposed copy of their input with snlm_iir_transpose_kernel
 // and read that instead):
-//   snlm_iir_fwd_kernel   the forward recursion of every offset, in
-//       segments; it stores only its state (w'(p-1), w'(p-2), w'(p-3)) in FP64
-//       at the start p = max(16 j, -L) of every block: 24 bytes per 16
+//   snlm_iir_fwd_kernel<S>  one workgroup of S waves per (64 lines, segment),
+//       wave s runs the forward recursion of offset s from a sample ring the
+//       waves share, and stores only its state (w'(p-1), w'(p-2), w'(p-3)) in
+//       FP64 at the start p = max(16 j, -L) of every block: 24 bytes per 16
 //       samples instead of the 64 of the values themselves.
 //   snlm_iir_nlm_kernel<S>  one workgroup of S waves per (64 lines, segment
 //       of outputs); wave s owns offset s.  It walks the segment's blocks
@@ -123,101 +124,97 @@ __device__ __forceinline__ double iir_lift(float xa, float xb) {
     return (double)(dd * dd);
 }
 
-// Workgroup t of the forward kernel: group t % ngroups, segment k = (t /
-// ngroups) % nseg, offset s = t / (ngroups * nseg) + 1.
-struct IirWave {
-    int group, k, s, lane, line, line0;
-};
-
-__device__ __forceinline__ IirWave iir_wave(const PassDesc& d, int nseg) {
-    IirWave o;
-    const int t = blockIdx.x;
-    o.group = t % d.ngroups;
-    o.k = (t / d.ngroups) % nseg;
-    o.s = t / (d.ngroups * nseg) + 1;
-    o.lane = threadIdx.x & (kLanes - 1);
-    o.line0 = o.group * kLanes;
-    o.line = min(o.line0 + o.lane, d.nlines - 1);
-    return o;
-}
-
 // Forward recursion of one segment, blocks [ja, jb) with ja = -1 + k
-// fwd_blocks: stores the state at the start of each of them.  The recursion
-// starts at vs = max(16 ja - W, -L) and runs in steps of 16 from g0 = vs
-// rounded down to a multiple of 16 (positions below vs are skipped), so that
-// every group of 16 steps begins at a block start.  Each lane streams its
-// line's samples through NPF register buffers (16 samples each, issued NPF
-// chunks ahead) into an LDS ring of two chunks: chunk c (positions g0 + 16c
-// ..) lands in slots (16c mod 32) .. + 15, and the chunk in slots 0..15 is
-// also copied to slots 32..47, so a group's 16 + s <= 32 samples sit at
-// consecutive slots.  A group at v0 reads chunks v0 and v0 + 16; the chunk at
-// v0 + 32 replaces chunk v0 once the group is done.  Every load takes the
-// same path (a reflected position is just another offset, FP16 a template
-// parameter), so the compiler counts the loads in flight and waits for the
-// oldest chunk only.
+// fwd_blocks, for all S offsets: workgroup (group, segment) of S waves, wave
+// q owns offset s = q + 1 and stores its state at the start of each block of
+// the segment.  The recursion starts at vs = max(16 ja - W, -L) and runs in
+// steps of 16 from g0 = vs rounded down to a multiple of 16 (positions below
+// vs are skipped), so that every group of 16 steps begins at a block start.
+// The waves share one LDS ring of the line's scaled samples: chunk c
+// (positions g0 + 16 c ..) sits at slots 16 c mod 64 (slots 64..79 repeat
+// 0..15), loaded once for all offsets, positions t = q, q + S, .. of a chunk
+// by wave q, two steps ahead through registers.  Step i writes chunk i + 2
+// (over chunk i - 2, last read in step i - 2), reads chunks i and i + 1, and
+// ends with a barrier; every wave runs the same steps.
 // Lanes past the last line repeat the last line's work and store its values
 // to its addresses (the same bits), so no store needs a lane mask.
-template <int NPF, bool F16>
-__global__ __launch_bounds__(kLanes) void snlm_iir_fwd_kernel(IirArgs a) {
+template <int S, bool F16>
+__global__ __launch_bounds__(kLanes* S) void snlm_iir_fwd_kernel(IirArgs a) {
     constexpr int C = kChunk;
-    constexpr int RING = 32;  // slots of distinct positions: [v0, v0 + 32) in use
-    static_assert(NPF >= 3 && NPF * C <= 64, "two chunks are taken before the first step; <= 63 loads in flight");
-    __shared__ float ring[(RING + C) * kLanes];  // ring[slot * 64 + lane]
+    constexpr int NR = (C + S - 1) / S;  // ring positions per wave and chunk
+    static_assert(S >= 1 && S <= kMaxS, "parameter range");
+    __shared__ float ring[80 * kLanes];  // ring[slot * 64 + lane]
     const PassDesc& d = a.pass;
-    const IirWave wv = iir_wave(d, a.nseg_f);
-    const int s = wv.s, lane = wv.lane;
-    const LineIO io = make_io<false>(d, wv.line0, lane, nullptr);
-    const CkIO ck = make_ck_io(a.ck, a.ck_bytes, wv.line, d.nlines, a.nblk);
+    const int group = blockIdx.x % d.ngroups;
+    const int k = blockIdx.x / d.ngroups;
+    const int q = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
+    const int lane = threadIdx.x & (kLanes - 1);
+    const int s = q + 1;
+    const int line0 = group * kLanes;
+    const int line = min(line0 + lane, d.nlines - 1);
+    const LineIO io = make_io<false>(d, line0, lane, nullptr);
+    const CkIO ck = make_ck_io(a.ck, a.ck_bytes, line, d.nlines, a.nblk);
     const float alpha = d.alpha;
     const double a1 = a.a1, a2 = a.a2, a3 = a.a3;
     const int n = d.n;
-    const int ja = -1 + wv.k * a.fwd_blocks;
+    const int ja = -1 + k * a.fwd_blocks;
     const int jb = min(ja + a.fwd_blocks, a.nblk - 1);
     const int vs = max(C * ja - a.W, -a.L);
     const int g0 = vs & ~(C - 1);
 
-    // the raw bits of 16 samples from position p (reflected near the ends)
-    auto load16 = [&](int p, unsigned* v) {
+    // this wave's share of chunk c, as the loaded bits
+    auto load_part = [&](int c, unsigned* xn) {
 #pragma unroll
-        for (int t = 0; t < C; ++t) {
-            const int pt = p + t;
-            const int so = ((unsigned)pt < (unsigned)n ? pt : refl(pt, n)) * io.in_pos_b;
+        for (int r = 0; r < NR; ++r) {
+            if (q + S * r >= C) continue;
+            const int p = g0 + C * c + q + S * r;
+            const int so = ((unsigned)p < (unsigned)n ? p : refl(p, n)) * io.in_pos_b;
             if constexpr (F16)
-                v[t] = __builtin_amdgcn_raw_buffer_load_b16(io.rin, io.in_base_b, so, 0);
+                xn[r] = __builtin_amdgcn_raw_buffer_load_b16(io.rin, io.in_base_b, so, 0);
             else
-                v[t] = __builtin_amdgcn_raw_buffer_load_b32(io.rin, io.in_base_b, so, 0);
+                xn[r] = __builtin_amdgcn_raw_buffer_load_b32(io.rin, io.in_base_b, so, 0);
         }
     };
-    auto sample = [&](unsigned bits) {
-        if constexpr (F16)
-            return (float)__builtin_bit_cast(_Float16, (unsigned short)bits);
-        else
-            return __builtin_bit_cast(float, bits);
-    };
-    unsigned vb[NPF][C];
+    auto put_part = [&](int c, const unsigned* xn) {
+        const int slot = (C * c) & 63;
 #pragma unroll
-    for (int q = 0; q < NPF; ++q) load16(g0 + C * q, vb[q]);
-    // chunk c (positions g0 + 16 c ..) from buffer c mod NPF into ring slots
-    // 16 c mod 32, then that buffer loads chunk c + NPF
-    auto take = [&](int c, int q) {
-        const int slot = (C * c) & (RING - 1);
-#pragma unroll
-        for (int t = 0; t < C; ++t) ring[(slot + t) * kLanes + lane] = alpha * sample(vb[q][t]);
-        if (slot == 0) {
-#pragma unroll
-            for (int t = 0; t < C; ++t) ring[(RING + t) * kLanes + lane] = alpha * sample(vb[q][t]);
+        for (int r = 0; r < NR; ++r) {
+            const int t = q + S * r;
+            if (t >= C) continue;
+            const float x = F16 ? (float)__builtin_bit_cast(_Float16, (unsigned short)xn[r]) : __builtin_bit_cast(float, xn[r]);
+            ring[(slot + t) * kLanes + lane] = alpha * x;
+            if (slot == 0) ring[(64 + t) * kLanes + lane] = alpha * x;
         }
-        load16(g0 + C * (c + NPF), vb[q]);
     };
-    take(0, 0);
-    take(1, 1);
+    unsigned xa[NR], xb[NR];
+    load_part(0, xa);
+    load_part(1, xb);
+    put_part(0, xa);
+    put_part(1, xb);
+    load_part(2, xa);
+    load_part(3, xb);
+    __syncthreads();
     const int i0 = vs - g0;
     const double d0 = iir_lift(ring[i0 * kLanes + lane], ring[(i0 + s) * kLanes + lane]) * a.inv_B;
     double w1 = d0, w2 = d0, w3 = d0;  // the steady state of D(vs)
-    // group i (positions g0 + 16 i ..) reads ring slots 16 i mod 32 ..
-    auto fwd16 = [&](int i, int skip) {
-        const float* rx = ring + ((C * i) & (RING - 1)) * kLanes + lane;
+    const int jg0 = g0 >> 4;
+    const int m = jb - jg0;  // group starts whose state the segment stores: 0 .. m - 1
+    // group i: store the state at its start (block jg0 + i, when it is one of
+    // the segment's; the others go past the buffer, where the bounds check
+    // drops them), put chunk i + 2 into the ring and load chunk i + 4, run
+    // the 16 steps (positions below vs skipped), barrier
+    auto group_step = [&](int i, unsigned* xr_regs) {
+        const int j = jg0 + i;
+        const bool mine = j >= ja && j < jb;
+        const int jc = min(max(j, ja), jb - 1);
+        ck.store_or_drop(s, jc, 0, w1, mine, a.ck_bytes);
+        ck.store_or_drop(s, jc, 1, w2, mine, a.ck_bytes);
+        ck.store_or_drop(s, jc, 2, w3, mine, a.ck_bytes);
+        put_part(i + 2, xr_regs);
+        load_part(i + 4, xr_regs);
+        const float* rx = ring + ((C * i) & 63) * kLanes + lane;
         const float* ry = rx + s * kLanes;
+        const int skip = max(vs - (g0 + C * i), 0);
 #pragma unroll
         for (int t = 0; t < C; ++t) {
             if (t < skip) continue;
@@ -226,39 +223,26 @@ __global__ __launch_bounds__(kLanes) void snlm_iir_fwd_kernel(IirArgs a) {
             w2 = w1;
             w1 = w;
         }
+        __syncthreads();
     };
-    // the state at the start of group i, block j = g0 / 16 + i, when it is
-    // one of the segment's (the others go past the buffer, where the bounds
-    // check drops them: every group issues the same memory operations)
-    const int jg0 = g0 >> 4;
-    auto store_state = [&](int i) {
-        const int j = jg0 + i;
-        const bool mine = j >= ja && j < jb;
-        const int jc = min(max(j, ja), jb - 1);  // an in-range block for the offset arithmetic
-        ck.store_or_drop(s, jc, 0, w1, mine, a.ck_bytes);
-        ck.store_or_drop(s, jc, 1, w2, mine, a.ck_bytes);
-        ck.store_or_drop(s, jc, 2, w3, mine, a.ck_bytes);
-    };
-    // group 0 (its first vs - g0 positions are before the recursion's start)
-    store_state(0);
-    const int m = jb - jg0;  // group starts whose state the segment stores: 0 .. m - 1
-    if (m > 1) {
-        fwd16(0, vs - g0);
-        take(2, 2 % NPF);
-        // groups 1 .. NPF * iters in whole runs of NPF (the host sizes
-        // segments so that only a line's first and last segment run past
-        // m - 1, computing a few groups nobody stores)
-        const int iters = (m - 2) / NPF + 1;
-        for (int it = 0; it < iters; ++it) {
-#pragma unroll
-            for (int q = 0; q < NPF; ++q) {
-                const int i = 1 + NPF * it + q;
-                store_state(i);
-                fwd16(1 + q, 0);  // ring slots depend on the parity of i only
-                take(i + 2, (q + 3) % NPF);
-            }
-        }
+    // groups 0 .. m - 2 run; the state at the start of group m - 1 is the
+    // last one stored (two groups per iteration: the register buffers
+    // alternate)
+    int i = 0;
+    for (; i + 1 < m - 1; i += 2) {
+        group_step(i, xa);
+        group_step(i + 1, xb);
     }
+    if (i < m - 1) {
+        group_step(i, xa);
+        ++i;
+    }
+    const int j = jg0 + i;
+    const bool mine = j >= ja && j < jb;
+    const int jc = min(max(j, ja), jb - 1);
+    ck.store_or_drop(s, jc, 0, w1, mine, a.ck_bytes);
+    ck.store_or_drop(s, jc, 1, w2, mine, a.ck_bytes);
+    ck.store_or_drop(s, jc, 2, w3, mine, a.ck_bytes);
 }
 
 // LDS of the NLM kernel: the sample ring (96 slots of 64 lanes: positions

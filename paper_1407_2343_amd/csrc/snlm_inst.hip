@@ -41,5 +41,7 @@ extern "C" void SNLM_CAT(snlm_register_s, SNLM_S)(snlm::KernelRegistry* reg) {
     snlm::register_k<0>(reg);
 #if SNLM_S > 0
     reg->iir[SNLM_S] = (const void*)&snlm::snlm_iir_nlm_kernel<SNLM_S>;
+    reg->iir_fwd[SNLM_S][0] = (const void*)&snlm::snlm_iir_fwd_kernel<SNLM_S, false>;
+    reg->iir_fwd[SNLM_S][1] = (const void*)&snlm::snlm_iir_fwd_kernel<SNLM_S, true>;
 #endif
 }
