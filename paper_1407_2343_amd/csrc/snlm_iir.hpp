@@ -249,10 +249,6 @@ __global__ __launch_bounds__(kLanes* S) void snlm_iir_fwd_kernel(IirArgs a) {
 // mod 64, slots 64..95 repeating 0..31) and the weights of S offsets for two
 // blocks (positions mod 32).
 constexpr int kIirXSlots = 96;
-template <int S>
-constexpr int iir_nlm_lds_bytes() {
-    return (kIirXSlots + S * 2 * kChunk) * kLanes * 4;
-}
 
 // Workgroup t: group t % ngroups, segment t / ngroups of seg outputs [a0, b0).
 // Wave q owns offset s = q + 1.  Blocks jbot = a0 / 16 - 1 (weights of the
