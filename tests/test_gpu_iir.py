@@ -231,3 +231,24 @@ def test_iir_errors():
     t = ctypes.c_uint64(0)
     assert snlm.lib().snlm_submit(ctx.handle, ctypes.byref(job), ctypes.byref(t)) == snlm.EINVAL
     ctx.close()
+
+
+def test_iir_random_sweep():
+    """Seeded random cases over the kernels' block, segment and ring logic:
+    shapes from single samples to a few hundred per axis (partial line groups,
+    lines shorter than the run-in, several segments), S from 1 to 16, beta from
+    0.5 to 64, both orders, FP32 and FP16 input; every pixel against the
+    oracle."""
+    rng = np.random.default_rng(2024)
+    ctx = _ctx(1 << 26)
+    for case in range(40):
+        H = int(rng.integers(1, 300))
+        W = int(rng.integers(1, 300))
+        S = int(rng.integers(1, 17))
+        beta = float(np.exp(rng.uniform(np.log(0.5), np.log(64.0))))
+        order = "row_col" if rng.random() < 0.5 else "col_row"
+        dtype = "f16" if rng.random() < 0.25 else "f32"
+        h = 150.0 * math.sqrt(beta) * float(rng.uniform(0.5, 2.0))
+        say("sweep case", case)
+        _check(ctx, _noisy(H, W, 20.0, 7000 + case), S, beta, h, order, dtype)
+    ctx.close()
