@@ -126,6 +126,43 @@ def test_batch_mixed_classes():
     ctx.close()
 
 
+@pytest.mark.parametrize("waves", [1, 2, 3, 4])
+def test_batch_fixed_waves_equals_plain(waves, tmp_path):
+    """Batched launches at a fixed number of persistent waves per SIMD, loaded
+    as the autotuner's record of each kernel class (box row_col, box col_row,
+    Gaussian row_col; S=10, K=3).  The planner cuts the line groups at
+    positions that depend on the worker count and, at two waves per SIMD, on
+    the 2 : 1 split of each SIMD's work between its first and second
+    workgroup; every output must still be bitwise its plain launch."""
+    import json
+    import torch
+    import paper_1407_2343_amd as snlm
+    classes = [("box", "row_col", 0, 0), ("box", "col_row", 0, 1), ("gauss", "row_col", 2, 0)]
+    path = str(tmp_path / "waves.json")
+    with open(path, "w") as f:
+        json.dump({"arch": "gfx950", "entries": [], "batch": [
+            {"bS": 10, "K": 3, "variant": var, "order": order, "waves_per_simd": waves}
+            for _, _, var, order in classes]}, f)
+    items = _ragged(18, 70 + waves, 64, 900)
+    xs = [torch.from_numpy(im).to("cuda:0") for im, _ in items]
+    outs = [torch.full_like(x, -5.0) for x in xs]
+    # the arena first: a context created for a larger one drops loaded tuning
+    ctx = _ctx(sum(snlm.workspace_bytes(*x.shape) for x in xs) + (1 << 20))
+    ctx.load_tuning(path)
+    cls = [classes[i % len(classes)] for i in range(len(items))]
+    jobs = snlm.job_array([ctx.job_for(x, o, 10, 3, 10 * sig, kern, order)
+                           for x, o, (_, sig), (kern, order, _, _) in zip(xs, outs, items, cls)])
+    ctx.denoise_jobs(jobs, sync=True)
+    for i, ((im, sig), x, o, (kern, order, _, _)) in enumerate(zip(items, xs, outs, cls)):
+        say("fixed waves", waves, i, kern, order, im.shape)
+        alone = ctx.denoise(x, 10, 3, 10 * sig, kern, order, sync=True)
+        assert torch.equal(o, alone), i
+        if i < len(classes):
+            ref = oracle.snlm(im.astype(np.float64), 10, 3, 10 * sig, kern, order)
+            assert max_abs(o.cpu().numpy(), ref) <= TOL, i
+    ctx.close()
+
+
 @pytest.mark.parametrize("mode", ["split", "fused"])
 def test_batch_degenerate_shapes(mode):
     """Degenerate images in one batched launch beside ordinary ones: 1 x 1,
