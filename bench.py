@@ -611,6 +611,34 @@ def recursive_gaussian(torch, snlm, n=2048, sigma=30.0):
     return rec
 
 
+def plain_512(torch, ctx):
+    """One 512 x 512 FP32 image (sigma 20, h = 10 sigma, S=10, K=3), box and
+    Gaussian, both orders: device time of each of 60 single launches (both
+    passes), events on the stream they run on."""
+    from paper_1407_2343_amd.synth import noisy_image
+    x512 = torch.from_numpy(noisy_image(512, 512, 20.0, seed=1001)).to("cuda:0")
+    o512 = torch.empty_like(x512)
+    res = {}
+    for kernel in ("box", "gauss"):
+        for order in ("row_col", "col_row"):
+            j512 = ctx.job_for(x512, o512, S, K, 200.0, kernel, order)
+            for _ in range(3):
+                ctx.denoise_job(j512)
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(60)]
+            for e0, e1 in evs:
+                e0.record()
+                ctx.denoise_job(j512)
+                e1.record()
+            torch.cuda.synchronize()
+            t = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+            p50, p99 = float(np.percentile(t, 50)), float(np.percentile(t, 99))
+            res["%s_%s" % (kernel, order)] = {
+                "mpx_per_s_p50": round(512 * 512 / (p50 * 1e-3) / 1e6, 1),
+                "ms_p50": round(p50, 4), "ms_p99": round(p99, 4), "launches": len(t)}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -631,6 +659,8 @@ def main():
                     help="print how the served kernels of a rocprofv3 kernel trace overlap in time (no GPU)")
     ap.add_argument("--iir-only", action="store_true",
                     help="run only the recursive-Gaussian section and print it")
+    ap.add_argument("--plain-only", action="store_true",
+                    help="run only the plain 512 x 512 single-image launches and print them (kernel traces)")
     ap.add_argument("--profile-batch", action="store_true",
                     help="only the batched steps (for rocprofv3 kernel traces and counters)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -672,6 +702,11 @@ def main():
         return
     if a.iir_only:
         print(json.dumps({"recursive_gaussian": recursive_gaussian(torch, snlm)}), flush=True)
+        return
+    if a.plain_only:
+        ctx = snlm.Context(arena_bytes=64 << 20)
+        print(json.dumps({"plain_512_mpx": plain_512(torch, ctx)}), flush=True)
+        ctx.close()
         return
     if a.issue_rate:
         rows = {}
@@ -736,28 +771,7 @@ def main():
     ms_plain, _ = time_steps(torch, plain_step, max(3, a.steps // 4), 1)
     plain_batch_mpx = total_px / (ms_plain * 1e-3) / 1e6
 
-    x512 = torch.from_numpy(noisy_image(512, 512, 20.0, seed=1001)).to("cuda:0")
-    o512 = torch.empty_like(x512)
-    plain512 = {}
-    for kernel in ("box", "gauss"):
-        for order in ("row_col", "col_row"):
-            j512 = ctx.job_for(x512, o512, S, K, 200.0, kernel, order)
-            # device time of each of 60 single launches (both passes), events on
-            # the stream they run on
-            for _ in range(3):
-                ctx.denoise_job(j512)
-            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                   for _ in range(60)]
-            for e0, e1 in evs:
-                e0.record()
-                ctx.denoise_job(j512)
-                e1.record()
-            torch.cuda.synchronize()
-            t = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
-            p50, p99 = float(np.percentile(t, 50)), float(np.percentile(t, 99))
-            plain512["%s_%s" % (kernel, order)] = {
-                "mpx_per_s_p50": round(512 * 512 / (p50 * 1e-3) / 1e6, 1),
-                "ms_p50": round(p50, 4), "ms_p99": round(p99, 4), "launches": len(t)}
+    plain512 = plain_512(torch, ctx)
 
     pairs = total_px * 2 * S
     alg_ops = pairs * PAIR_VALU
