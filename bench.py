@@ -13,11 +13,12 @@ images one by one, and one 512 x 512 image in the four kernel/order
 variants), the roofline of the batched kernels (device time from HIP events
 on the stream they run on), the serving workload (2000 requests, Poisson
 arrivals, p50/p99 latency and Mpixel/s, against FIFO plain launches), the
-precision variants on a 4096 x 4096 image, the SURE-optimal combination of
+precision variants' throughput on 2048 x 2048 and 4096 x 4096 images (their
+error against the FP64 oracle is a GPU test), the SURE-optimal combination of
 the two orders on a 2048 x 2048 image (``sure_combination``), the recursive
 Gaussian patch kernel on a 2048 x 2048 image (``recursive_gaussian``), and the
 FP64 oracle timed on the host cores on a bounded sample of the batch
-(``cpu_baseline``).
+(``cpu_baseline``, the only part that runs the oracle).
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-serve] [--no-precision] [--no-sure]
                     [--no-iir] [--iir-only] [--no-cpu]
@@ -432,54 +433,44 @@ def serving_overlap(path):
 
 # --------------------------------------------------------------- precision --
 def precision(torch, snlm, sizes=(2048, 4096), sigma=30.0):
-    """n x n images, sigma 30, S=15, K=4, box, h = 10 sigma: {FP16, FP32
-    storage} x {block-restarted, plain, Kahan} running sums; max-abs and RMS
-    error over every pixel against the FP64 oracle run on the values the GPU
-    read, and for FP16 also against the FP32 input before rounding."""
-    import oracle
+    """n x n images, sigma 30, S=15, K=4, box, h = 10 sigma: Mpixel/s of
+    {FP16, FP32 storage} x {block-restarted, plain, Kahan} running sums.  Their
+    error against the FP64 oracle over every pixel is a GPU test of the same
+    images (tests/test_gpu_systems.py, test_precision_variants_whole_image);
+    here, each variant's distance from the FP32 Kahan result, for scale."""
     from paper_1407_2343_amd.synth import noisy_image
     out = {}
     for n in sizes:
         img = noisy_image(n, n, sigma, seed=3001 + n)
         ctx = snlm.Context(arena_bytes=snlm.workspace_bytes(n, n) + (1 << 20))
-        ref32 = None
-        rec_n = {}
+        ys, rec_n = {}, {}
         for dtype in ("f32", "f16"):
             x = torch.from_numpy(img.astype(np.float16 if dtype == "f16" else np.float32)).to("cuda:0")
-            xr = x.cpu().numpy().astype(np.float64)
-            t0 = time.perf_counter()
-            ref = oracle.snlm(xr, 15, 4, 10 * sigma, "box", "row_col")
-            log("oracle %dx%d %s: %.1f s" % (n, n, dtype, time.perf_counter() - t0))
-            if dtype == "f32":
-                ref32 = ref
-            for sm in ("block", "plain", "kahan"):
+            for sm in ("kahan", "block", "plain"):
                 y_t = torch.empty((n, n), device="cuda:0")
                 j = ctx.job_for(x, y_t, 15, 4, 10 * sigma, "box", "row_col", sm)
                 ms, _ = time_steps(torch, lambda: ctx.denoise_job(j), 3, 1)
-                y = y_t.cpu().numpy().astype(np.float64)
-                e = y - ref
-                rec = {"max_abs": float(np.max(np.abs(e))), "rms": float(np.sqrt(np.mean(e * e))),
-                       "mpx_per_s": round(n * n / ms / 1e3, 1)}
-                if dtype == "f16":
-                    e2 = y - ref32
-                    rec["max_abs_vs_unrounded"] = float(np.max(np.abs(e2)))
-                    rec["rms_vs_unrounded"] = float(np.sqrt(np.mean(e2 * e2)))
-                rec_n["%s_%s" % (dtype, sm)] = rec
+                name = "%s_%s" % (dtype, sm)
+                ys[name] = y_t.cpu().numpy().astype(np.float64)
+                e = ys[name] - ys["f32_kahan"]
+                rec_n[name] = {"mpx_per_s": round(n * n / ms / 1e3, 1),
+                               "max_abs_vs_f32_kahan": float(np.max(np.abs(e))),
+                               "rms_vs_f32_kahan": float(np.sqrt(np.mean(e * e)))}
         ctx.close()
         out["%dx%d" % (n, n)] = rec_n
     return {"image": "sigma=%g S=15 K=4 box row_col h=10 sigma" % sigma,
-            "pixels_compared": "every pixel of each image", "variants": out}
+            "error_vs_fp64_oracle": "every pixel, tests/test_gpu_systems.py::test_precision_variants_whole_image",
+            "variants": out}
 
 
 # ----------------------------------------------------------- SURE combination --
-def sure_combination(torch, snlm, n=2048, sigma=30.0, nsample=6):
+def sure_combination(torch, snlm, n=2048, sigma=30.0):
     """SNLM with the SURE-optimal combination of the two orders (Alg. 4) on an
     n x n image with a known clean image (eq. noise), S=10, K=3, box, h = 10
     sigma: Mpixel/s of the whole call (four divergence-carrying passes, the
     FP64 image sums, the 2x2 solve and the combination), theta, the MSE of each
     order and of the combination against the clean image, and the SURE
-    estimate; parity at sampled pixels of f_cr against the FP64 oracle."""
-    import oracle
+    estimate.  Parity against the FP64 oracle is tests/test_gpu_sure.py."""
     from paper_1407_2343_amd.synth import clean_image
     rng = np.random.default_rng(6001)
     f0 = clean_image(n, n, rng)
@@ -504,13 +495,10 @@ def sure_combination(torch, snlm, n=2048, sigma=30.0, nsample=6):
     mse = float(np.mean((y - f0d) ** 2))
     phi = float(np.mean((y - fd) ** 2) - sigma ** 2
                 + 2 * sigma ** 2 / fd.size * (theta[0] * d_rc.sum() + theta[1] * d_cr.sum()))
-    pts = [(0, 0), (n - 1, n - 1)] + [(int(rng.integers(0, n)), int(rng.integers(0, n)))
-                                      for _ in range(nsample - 2)]
-    err = max(abs(f_cr[r, c] - oracle.pixel(fd, r, c, S, K, 10 * sigma, "box", "col_row")) for r, c in pts)
     rec = {"image": "%dx%d sigma=%g S=%d K=%d box h=10 sigma" % (n, n, sigma, S, K),
            "mpx_per_s": round(n * n / ms / 1e3, 1), "ms": round(ms, 3),
            "theta": [round(t, 6) for t in theta], "mse_combined": round(mse, 4),
-           "sure": round(phi, 4), "f_cr_max_abs_vs_oracle_sampled": err}
+           "sure": round(phi, 4)}
     if f_rc is not None:
         rec["mse_row_col"] = round(float(np.mean((f_rc - f0d) ** 2)), 4)
     rec["mse_col_row"] = round(float(np.mean((f_cr - f0d) ** 2)), 4)
@@ -541,15 +529,13 @@ def recursive_gaussian(torch, snlm, n=2048, sigma=30.0):
     """The Gaussian patch kernel by the recursive filter (kernel "gauss_iir")
     on an n x n image, S=10, h = 10 sigma sqrt(sqrt(2 pi) beta / 7): Mpixel/s
     at beta = 2 and at beta = 8 (a width the exact FIR, K <= 8, cannot reach),
-    beside the exact FIR at beta = 2 with K = 4 and K = 6; max-abs against the
-    FP64 oracle over the whole image, and the recursive kernel's distance from
-    the exact FIR with taps out to 3 beta at beta = 1, 2, 8/3 (its
-    approximation error, not a parity figure), beside the box kernel's."""
-    import oracle
+    beside the exact FIR at beta = 2 with K = 4 and K = 6, and the recursive
+    kernel's distance from the exact FIR with taps out to 3 beta at beta = 1,
+    2, 8/3 (its approximation error, not a parity figure), beside the box
+    kernel's.  Parity against the FP64 oracle is tests/test_gpu_iir.py."""
     from paper_1407_2343_amd.synth import noisy_image
     img = noisy_image(n, n, sigma, seed=7001)
     x = torch.from_numpy(img).to("cuda:0")
-    xr = x.cpu().numpy().astype(np.float64)
     ctx = snlm.Context(arena_bytes=snlm.workspace_bytes(n, n) + (1 << 20))
 
     def h_for(beta):
@@ -564,9 +550,6 @@ def recursive_gaussian(torch, snlm, n=2048, sigma=30.0):
         ms, _ = time_steps(torch, lambda: ctx.denoise_job(j), 10, 2)
         outs[name] = y.cpu().numpy().astype(np.float64)
         rec[name] = {"mpx_per_s": round(n * n / ms / 1e3, 1), "ms": round(ms, 3)}
-    for name, beta in (("iir_beta2", 2.0), ("iir_beta8", 8.0)):
-        ref = oracle.snlm(xr, S, 0, h_for(beta), "gauss_iir", "row_col", beta=beta)
-        rec[name]["max_abs_vs_oracle"] = float(np.max(np.abs(outs[name] - ref)))
     # HBM roofline of the recursive path at beta = 2 (both passes): per pass,
     # the forward recursion reads x and writes its FP64 state at every block
     # start (3 S ((n + L - 1) / 16 + 2) words per line), the NLM kernel reads

@@ -107,3 +107,31 @@ def test_serving_overlap(tmp_path):
     r = bench.serving_overlap(path)
     assert r["dispatches"] == 2 and r["busy_us"] == 20.0 and r["max_concurrent"] == 2
     assert r["overlap_share_of_busy"] == 0.25
+
+
+def _names_oracle(node):
+    import ast
+    for n in ast.walk(node):
+        if isinstance(n, ast.Name) and n.id == "oracle":
+            return True
+        if isinstance(n, (ast.Import, ast.ImportFrom)):
+            mods = [a.name for a in n.names] + ([n.module] if isinstance(n, ast.ImportFrom) and n.module else [])
+            if any(m == "oracle" or m.startswith("oracle.") for m in mods):
+                return True
+    return False
+
+
+def test_oracle_only_in_cpu_baseline():
+    """The oracle is test infrastructure: in bench.py only the cpu_baseline
+    leg may import or call it, and no module of the GPU library names it."""
+    import ast
+    tree = ast.parse(open(os.path.join(ROOT, "bench.py")).read())
+    users = [n.name for n in tree.body if isinstance(n, (ast.FunctionDef, ast.AsyncFunctionDef)) and _names_oracle(n)]
+    top = [n for n in tree.body if not isinstance(n, (ast.FunctionDef, ast.AsyncFunctionDef)) and _names_oracle(n)]
+    assert users == ["cpu_baseline"] and not top, users
+    pkg = os.path.join(ROOT, "paper_1407_2343_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith(".py"):
+                path = os.path.join(dirpath, f)
+                assert not _names_oracle(ast.parse(open(path).read())), path

@@ -288,28 +288,37 @@ def _precision_case(n, dtype):
         t0 = time.time()
         ref = oracle.snlm(xr, 15, 4, 300.0, "box", "row_col")
         say("oracle %dx%d %s in %.1f s" % (n, n, dtype, time.time() - t0))
-        _ORACLE_CACHE.clear()  # keep one 4096^2 reference at a time
+        for k in [k for k in _ORACLE_CACHE if k[0] != n]:
+            del _ORACLE_CACHE[k]  # keep the references of one size at a time
         _ORACLE_CACHE[key] = (x, ref)
     return _ORACLE_CACHE[key]
 
 
-@pytest.mark.parametrize("n", [2048, 4096])
-@pytest.mark.parametrize("dtype", ["f32", "f16"])
 @pytest.mark.parametrize("sum", ["block", "plain", "kahan"])
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+@pytest.mark.parametrize("n", [2048, 4096])
 def test_precision_variants_whole_image(n, dtype, sum):
     """The precision workload at both of its sizes (sigma 30, S=15, K=4, box):
     FP16 / FP32 storage x block-restarted / plain / Kahan running sums, every
     output pixel against the FP64 oracle run on exactly the values the GPU
-    read (max-abs <= 1e-3), with the RMS error reported."""
+    read (max-abs <= 1e-3), with the RMS error reported; for FP16 storage
+    also the distance from the oracle of the FP32 input before rounding (the
+    storage format's own error, reported, not bounded by the tolerance)."""
     import torch
     import paper_1407_2343_amd as snlm
     x, ref = _precision_case(n, dtype)
     ctx = _ctx(snlm.workspace_bytes(n, n) + (1 << 20))
-    say("precision", n, dtype, sum)
     y = ctx.denoise(x, 15, 4, 300.0, "box", "row_col", sum=sum, sync=True).cpu().numpy().astype(np.float64)
     e = y - ref
     worst, rms = float(np.max(np.abs(e))), float(np.sqrt(np.mean(e * e)))
-    say("  whole-image max-abs %.3g rms %.3g" % (worst, rms))
+    line = "precision %dx%d %s %s: max-abs %.3g rms %.3g vs the oracle of the stored values" % (
+        n, n, dtype, sum, worst, rms)
+    if dtype == "f16":
+        _, ref32 = _precision_case(n, "f32")
+        e2 = y - ref32
+        line += "; vs the FP32 input's oracle max-abs %.3g rms %.3g" % (
+            float(np.max(np.abs(e2))), float(np.sqrt(np.mean(e2 * e2))))
+    say(line)
     assert worst <= TOL
     ctx.close()
 
