@@ -642,6 +642,8 @@ def main():
                     help="print how the served kernels of a rocprofv3 kernel trace overlap in time (no GPU)")
     ap.add_argument("--iir-only", action="store_true",
                     help="run only the recursive-Gaussian section and print it")
+    ap.add_argument("--sure-only", action="store_true",
+                    help="run only the SURE-combination and SNLM[f] section and print it (kernel traces)")
     ap.add_argument("--plain-only", action="store_true",
                     help="run only the plain 512 x 512 single-image launches and print them (kernel traces)")
     ap.add_argument("--profile-batch", action="store_true",
@@ -685,6 +687,9 @@ def main():
         return
     if a.iir_only:
         print(json.dumps({"recursive_gaussian": recursive_gaussian(torch, snlm)}), flush=True)
+        return
+    if a.sure_only:
+        print(json.dumps({"sure_combination": sure_combination(torch, snlm)}), flush=True)
         return
     if a.plain_only:
         ctx = snlm.Context(arena_bytes=64 << 20)

@@ -255,10 +255,11 @@ const void* kernel_fn(const snlm_job& j, int pass) {
     return g_reg.fn[j.S][j.K][variant_of(j)][pass_rows(j, pass) ? 1 : 0];
 }
 
-// Divergence-carrying kernel of a job (both passes use it; no LDS tiles).
-const void* div_fn(const snlm_job& j) {
+// Divergence-carrying kernel of one pass of a job (the row-pass variant when
+// its lines are rows).
+const void* div_fn(const snlm_job& j, int pass) {
     init_registry();
-    return g_reg.div[j.S][j.K][j.kernel == SNLM_GAUSS ? 1 : 0];
+    return g_reg.div[j.S][j.K][j.kernel == SNLM_GAUSS ? 1 : 0][pass_rows(j, pass) ? 1 : 0];
 }
 
 // Batched launches group jobs whose passes use the same two kernels.
@@ -1906,8 +1907,7 @@ int sure_enqueue(snlm_ctx* c, const snlm_job* j, float sigma, float* dst, int ld
                  double* stats) {
     size_t off[8];
     snlm_sure_layout(j->H, j->W, off);
-    const void* fn = div_fn(*j);
-    if (!fn) return fail(c, SNLM_EDEVICE, "kernel variant not compiled");
+    if (!div_fn(*j, 0) || !div_fn(*j, 1)) return fail(c, SNLM_EDEVICE, "kernel variant not compiled");
     HIP_CHECK(c, hipSetDevice(c->device));
     char* ws = c->arena;
     float* mid = (float*)(ws + off[0]);
@@ -1944,7 +1944,7 @@ int sure_enqueue(snlm_ctx* c, const snlm_job* j, float sigma, float* dst, int ld
             a.d_pos = rows ? 1 : Wp;
             void* args[] = {&a};
             const int grid = a.pass.ngroups * a.pass.nseg;
-            HIP_CHECK(c, hipLaunchKernel(fn, dim3(grid), dim3(snlm::kLanes), args, 0, st));
+            HIP_CHECK(c, hipLaunchKernel(div_fn(jj, pass), dim3(grid), dim3(snlm::kLanes), args, 0, st));
         }
     }
     snlm::StatArgs sa;

@@ -278,11 +278,14 @@ struct LineIO {
 
     // Second half: for a staged chunk, wait for the loads and read this lane's
     // own samples p .. p + kChunk - 1 out of the tile.
-    // stores_after: vector stores issued since the chunk's loads (the loads
-    // complete in order before them, so they need not be waited for).
-    __device__ __forceinline__ void finish_chunk(int p, float* v, bool four_stores_after) const {
+    // stores_after: vector stores issued since the chunk's loads, 0, 4 (one
+    // staged output tile) or 8 (two); the loads complete in order before
+    // them, so they need not be waited for.
+    __device__ __forceinline__ void finish_chunk(int p, float* v, int stores_after) const {
         if (!chunk_staged(p)) return;
-        if (four_stores_after)
+        if (stores_after >= 8)
+            __builtin_amdgcn_s_waitcnt(0x0F78);  // vmcnt(8): loads landed, the 8 stores may fly
+        else if (stores_after >= 4)
             __builtin_amdgcn_s_waitcnt(0x0F74);  // vmcnt(4): loads landed, the 4 stores may fly
         else
             __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
@@ -442,7 +445,7 @@ __device__ __forceinline__ void run_segment(const PassDesc& d, const LineIO& io,
     // ---- main chunks ----
     bool staged_store_last = false;  // the previous chunk ended with 4 tile stores
     for (c0 = seg_a;; c0 += C) {
-        io.finish_chunk(c0 + S + K, nx, staged_store_last);
+        io.finish_chunk(c0 + S + K, nx, staged_store_last ? 4 : 0);
         advance_chunk<S, XO>(xs, P, Q, nx, alpha);
         const bool has_next = c0 + C < seg_b;
         // Column passes fetch the next chunk unconditionally (a chunk past the

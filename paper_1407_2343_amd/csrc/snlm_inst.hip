@@ -15,11 +15,15 @@ void register_k(KernelRegistry* reg) {
         const void* f = (const void*)&snlm_kernel<0, 0, false, false, false, false>;
         for (int v = 0; v < kNumVariants; ++v)
             for (int r = 0; r < 2; ++r) reg->fn[0][K][v][r] = f;
-        reg->div[0][K][0] = reg->div[0][K][1] = (const void*)&snlm_div_kernel<0, 0, false>;
+        for (int g = 0; g < 2; ++g)
+            for (int r = 0; r < 2; ++r) reg->div[0][K][g][r] = (const void*)&snlm_div_kernel<0, 0, false, false>;
     } else {
         // snlm_kernel<S, K, GAUSS, KAHAN, RESTART, ROWS>
-        reg->div[SNLM_S][K][0] = (const void*)&snlm_div_kernel<SNLM_S, K, false>;
-        reg->div[SNLM_S][K][1] = (const void*)&snlm_div_kernel<SNLM_S, K, true>;
+        // snlm_div_kernel<S, K, GAUSS, ROWS>
+        reg->div[SNLM_S][K][0][0] = (const void*)&snlm_div_kernel<SNLM_S, K, false, false>;
+        reg->div[SNLM_S][K][0][1] = (const void*)&snlm_div_kernel<SNLM_S, K, false, true>;
+        reg->div[SNLM_S][K][1][0] = (const void*)&snlm_div_kernel<SNLM_S, K, true, false>;
+        reg->div[SNLM_S][K][1][1] = (const void*)&snlm_div_kernel<SNLM_S, K, true, true>;
         reg->fn[SNLM_S][K][kVarBox][0] = (const void*)&snlm_kernel<SNLM_S, K, false, false, true, false>;
         reg->fn[SNLM_S][K][kVarBox][1] = (const void*)&snlm_kernel<SNLM_S, K, false, false, true, true>;
         reg->fn[SNLM_S][K][kVarBoxKahan][0] = (const void*)&snlm_kernel<SNLM_S, K, false, true, false, false>;

@@ -16,12 +16,13 @@ enum Variant { kVarBox = 0, kVarBoxKahan = 1, kVarGauss = 2, kVarBoxPlain = 3, k
 
 // fn[S][K][variant][rows]: rows = 1 is the variant for passes whose lines are
 // contiguous in memory (LDS transpose tiles), rows = 0 for column passes.
-// div[S][K][gauss]: divergence-carrying passes (block-restarted box, or Gauss).
+// div[S][K][gauss][rows]: divergence-carrying passes (block-restarted box, or
+// Gauss); rows as for fn.
 // iir[S]: the recursive-Gaussian pass's backward recursion and 1D NLM (S >= 1);
 // iir_fwd[S][f16]: its forward recursion.
 struct KernelRegistry {
     const void* fn[kMaxS + 1][kMaxK + 1][kNumVariants][2];
-    const void* div[kMaxS + 1][kMaxK + 1][2];
+    const void* div[kMaxS + 1][kMaxK + 1][2][2];
     const void* iir[kMaxS + 1];
     const void* iir_fwd[kMaxS + 1][2];
 };

@@ -27,7 +27,7 @@ namespace snlm {
 constexpr float kTwoLn2 = 1.3862943611198906f;
 
 struct DivArgs {
-    PassDesc pass;        // samples in and out, as for a plain pass (no LDS tiles)
+    PassDesc pass;        // samples in and out, as for a plain pass
     const float* din;     // divergence carried in; nullptr: 1
     float* dout;          // divergence out
     uint32_t din_bytes, dout_bytes;
@@ -35,23 +35,43 @@ struct DivArgs {
     int32_t d_pos;        // element stride between samples
 };
 
-struct DivLineIO {
-    __amdgpu_buffer_rsrc_t rin, rout;
+// The divergence carried in, one chunk of a lane's line at a time.  Row
+// passes (samples contiguous, 16-byte aligned) read a whole chunk with four
+// 16-byte loads per lane instead of sixteen 4-byte ones.
+struct DivIn {
+    __amdgpu_buffer_rsrc_t r;
     int32_t base_b, pos_b;
-    bool has_in;
+    bool has, vec;
 
     __device__ __forceinline__ float load(int p) const {
-        if (!has_in) return 1.0f;
-        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rin, base_b + p * pos_b, 0, 0));
+        if (!has) return 1.0f;
+        return as_float(__builtin_amdgcn_raw_buffer_load_b32(r, base_b + p * pos_b, 0, 0));
     }
-    __device__ __forceinline__ void store(int p, float v) const {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rout, base_b + p * pos_b, 0, 0);
+    // positions past the line's end read its last sample (never stored)
+    __device__ __forceinline__ void load_chunk(int c0, int n, float* dv) const {
+        if (!has) {
+#pragma unroll
+            for (int i = 0; i < kChunk; ++i) dv[i] = 1.0f;
+        } else if (vec && c0 + kChunk <= n) {
+#pragma unroll
+            for (int q = 0; q < kChunk / 4; ++q) {
+                const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(r, base_b + (c0 + 4 * q) * 4, 0, 0);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) dv[4 * q + e] = as_float(w[e]);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < kChunk; ++i) dv[i] = load(min(c0 + i, n - 1));
+        }
     }
 };
 
+// io: samples in and y out; dio: the same lines' divergence out (io with the
+// divergence buffer as its output; row passes stage it through the same LDS
+// output tile as y).
 template <int S, int K, bool GAUSS>
-__device__ __forceinline__ void run_segment_div(const PassDesc& d, const LineIO& io, const DivLineIO& dio,
-                                                bool active, int seg_a, int seg_b) {
+__device__ __forceinline__ void run_segment_div(const PassDesc& d, const LineIO& io, const LineIO& dio,
+                                                const DivIn& din, int seg_a, int seg_b) {
     constexpr int C = kChunk;
     constexpr int NX = C + S + 2 * K + 1;  // x window: positions c0-K-1 .. c0+C+S+K-1
     constexpr int NP = C + S;              // centres c0 .. c0+C+S-1
@@ -71,8 +91,22 @@ __device__ __forceinline__ void run_segment_div(const PassDesc& d, const LineIO&
 #pragma unroll
     for (int k = 0; k <= K; ++k) g[k] = d.taps[k];
 
+    // The pre-chunk's window and the first chunk's loads, as in the plain pass.
     int c0 = seg_a - C;
-    io.template load<NX>(c0 - K - 1, xs);
+    if (io.stage_in) {
+        if (io.template window_staged<NX>(c0 - K - 1)) {
+            io.template start_window<NX>(c0 - K - 1);
+            const bool tile_loads = io.chunk_staged(seg_a + S + K);
+            io.issue_chunk(seg_a + S + K, nx);
+            io.template finish_window<NX>(c0 - K - 1, xs, tile_loads);
+        } else {
+            io.template load<NX>(c0 - K - 1, xs);
+            io.issue_chunk(seg_a + S + K, nx);
+        }
+    } else {
+        io.issue_chunk(seg_a + S + K, nx);
+        io.template load<NX>(c0 - K - 1, xs);
+    }
 #pragma unroll
     for (int j = 0; j < NX; ++j) xs[j] = alpha * xs[j];
 #pragma unroll
@@ -86,7 +120,6 @@ __device__ __forceinline__ void run_segment_div(const PassDesc& d, const LineIO&
         U1[i] = 0.0f;
         U2[i] = 0.0f;
     }
-    io.issue_chunk(seg_a + S + K, nx);
 
     // Pair (i, i+s) of weight w: its partner terms for centre i+s, and, when
     // centre_i, its terms for centre i.
@@ -135,7 +168,9 @@ __device__ __forceinline__ void run_segment_div(const PassDesc& d, const LineIO&
     }
 
     // ---- main chunks ----
+    int stores_last = 0;  // staged stores issued after the pending chunk's loads
     for (c0 = seg_a;; c0 += C) {
+        io.finish_chunk(c0 + S + K, nx, stores_last);
         advance_chunk<S, XO>(xs, P, Q, nx, alpha);
 #pragma unroll
         for (int i = 0; i < S; ++i) M[i] = M[i + C];
@@ -152,10 +187,10 @@ __device__ __forceinline__ void run_segment_div(const PassDesc& d, const LineIO&
             U2[i] = 0.0f;
         }
         const bool has_next = c0 + C < seg_b;
-        if (has_next) io.issue_chunk(c0 + C + S + K, nx);
+        // (column passes fetch the next chunk unconditionally, as the plain pass)
+        if (has_next || !io.stage_in) io.issue_chunk(c0 + C + S + K, nx);
         float dv[C];
-#pragma unroll
-        for (int i = 0; i < C; ++i) dv[i] = dio.load(min(c0 + i, d.n - 1));
+        din.load_chunk(c0, d.n, dv);
 
 #pragma unroll
         for (int s = 1; s <= S; ++s) {
@@ -188,33 +223,37 @@ __device__ __forceinline__ void run_segment_div(const PassDesc& d, const LineIO&
             const float t = __builtin_fmaf(-dx, U2[i], U1[i]);
             dd[i] = dv[i] * (__builtin_fmaf(kTwoLn2, t + spread, 1.0f) * rq);
         }
-        io.store_chunk(c0, seg_b, y);
-        if (active) {
-#pragma unroll
-            for (int i = 0; i < C; ++i)
-                if (c0 + i < seg_b) dio.store(c0 + i, dd[i]);
+        // Lanes past the last line repeat its work: their stores write the
+        // same bits to the same addresses, as in the plain pass.
+        if (!has_next) {
+            io.store_chunk(c0, seg_b, y);
+            dio.store_chunk(c0, seg_b, dd);
+            break;
         }
-        if (!has_next) break;
+        const bool y_staged = io.store_full(c0, y);
+        const bool d_staged = dio.store_full(c0, dd);
+        stores_last = y_staged && d_staged ? 8 : 0;
     }
 }
 
 // S = 0: y = x and dy/dx = 1.
-__device__ __forceinline__ void run_copy_div(const LineIO& io, const DivLineIO& dio, bool active, int seg_a,
+__device__ __forceinline__ void run_copy_div(const LineIO& io, const LineIO& dio, const DivIn& din, int seg_a,
                                              int seg_b) {
     for (int p = seg_a; p < seg_b; ++p) {
         float v[1];
         io.template load<1>(p, v);
-        const float dv = dio.load(p);
-        if (active) {
-            io.store(p, v[0]);
-            dio.store(p, dv);
-        }
+        const float dv = din.load(p);
+        io.store(p, v[0]);
+        dio.store(p, dv);
     }
 }
 
-// One workgroup (one wave) per (line group, segment), as the direct plain pass.
-template <int S, int K, bool GAUSS>
+// One workgroup (one wave) per (line group, segment), as the direct plain
+// pass.  ROWS: lines contiguous in memory; samples in, y out and the
+// divergence out go through the LDS tiles of the plain row kernel.
+template <int S, int K, bool GAUSS, bool ROWS>
 __global__ __launch_bounds__(kLanes) void snlm_div_kernel(DivArgs a) {
+    __shared__ __attribute__((aligned(16))) float tiles[ROWS ? row_lds_floats(kChunk + S + 2 * K + 1) : 1];
     const PassDesc& d = a.pass;
     const int t = blockIdx.x;
     const int group = t % d.ngroups;
@@ -222,19 +261,25 @@ __global__ __launch_bounds__(kLanes) void snlm_div_kernel(DivArgs a) {
     const int seg_b = min(seg_a + d.seg_len, d.n);
     const int lane = threadIdx.x & (kLanes - 1);
     const int line0 = group * kLanes;
-    const bool active = line0 + lane < d.nlines;
-    const LineIO io = make_io<false>(d, line0, lane, nullptr);
-    DivLineIO dio;
+    const LineIO io = make_io<ROWS>(d, line0, lane, tiles);
     const int line = min(line0 + lane, d.nlines - 1);
-    dio.rin = make_rsrc(a.din, a.din ? a.din_bytes : 0u);
+    LineIO dio = io;
     dio.rout = make_rsrc(a.dout, a.dout_bytes);
-    dio.base_b = line * a.d_line * 4;
-    dio.pos_b = a.d_pos * 4;
-    dio.has_in = a.din != nullptr;
+    dio.out_base_b = line * a.d_line * 4;
+    dio.out_pos_b = a.d_pos * 4;
+    dio.out_line = a.d_line;
+    dio.out_bytes = a.dout_bytes;
+    dio.stage_out = ROWS && a.d_pos == 1 && (a.d_line & 3) == 0 && ((uintptr_t)a.dout & 15) == 0;
+    DivIn din;
+    din.r = make_rsrc(a.din, a.din ? a.din_bytes : 0u);
+    din.base_b = line * a.d_line * 4;
+    din.pos_b = a.d_pos * 4;
+    din.has = a.din != nullptr;
+    din.vec = ROWS && a.d_pos == 1 && (a.d_line & 3) == 0 && ((uintptr_t)a.din & 15) == 0;
     if constexpr (S == 0)
-        run_copy_div(io, dio, active, seg_a, seg_b);
+        run_copy_div(io, dio, din, seg_a, seg_b);
     else
-        run_segment_div<S, K, GAUSS>(d, io, dio, active, seg_a, seg_b);
+        run_segment_div<S, K, GAUSS>(d, io, dio, din, seg_a, seg_b);
 }
 
 }  // namespace snlm
