@@ -77,25 +77,45 @@ struct StatArgs {
     int H, W, ld_f, ld_rc, ld_x, f16;
 };
 
-// Per-block FP64 partial sums over a grid-stride walk of the pixels.
+constexpr int kStatCols = 4 * kStatThreads;  // columns of one unit of work
+
+// The pixels of unit u: row u / nch, columns kStatCols (u % nch) + [0,
+// kStatCols) of it (nch units per row); thread t takes columns t, t + 256, ...
+template <bool F16>
+__device__ __forceinline__ void stat_units(const StatArgs& a, double* acc) {
+    const int nch = (a.W + kStatCols - 1) / kStatCols;
+    const int units = a.H * nch;
+    for (int u = blockIdx.x; u < units; u += kStatBlocks) {
+        const int r = u / nch;
+        const int c0 = (u - r * nch) * kStatCols + threadIdx.x;
+        const long rf = (long)r * a.ld_f, rr = (long)r * a.ld_rc, rx = (long)r * a.ld_x;
+#pragma unroll
+        for (int k = 0; k < kStatCols / kStatThreads; ++k) {
+            const int c = c0 + k * kStatThreads;
+            if (c >= a.W) break;
+            const double x = F16 ? (double)((const _Float16*)a.f)[rf + c] : (double)((const float*)a.f)[rf + c];
+            const double fu = a.frc[rr + c];
+            const double fv = a.fcr[rx + c];
+            acc[0] += fu * fu;
+            acc[1] += fu * fv;
+            acc[2] += fv * fv;
+            acc[3] += x * fu;
+            acc[4] += x * fv;
+            acc[5] += a.drc[rx + c];
+            acc[6] += a.dcr[rx + c];
+        }
+    }
+}
+
+// Per-block FP64 partial sums: block b takes units b, b + kStatBlocks, ...
+// (a fixed assignment, so the sums do not depend on the device).
 __global__ __launch_bounds__(kStatThreads) void snlm_sure_stats(StatArgs a) {
     __shared__ double red[kStatThreads][kStats + 1];
     double acc[kStats] = {0, 0, 0, 0, 0, 0, 0};
-    const long n = (long)a.H * a.W;
-    for (long i = (long)blockIdx.x * kStatThreads + threadIdx.x; i < n; i += (long)kStatBlocks * kStatThreads) {
-        const int r = (int)(i / a.W), c = (int)(i % a.W);
-        const double x = a.f16 ? (double)((const _Float16*)a.f)[(long)r * a.ld_f + c]
-                               : (double)((const float*)a.f)[(long)r * a.ld_f + c];
-        const double u = a.frc[(long)r * a.ld_rc + c];
-        const double v = a.fcr[(long)r * a.ld_x + c];
-        acc[0] += u * u;
-        acc[1] += u * v;
-        acc[2] += v * v;
-        acc[3] += x * u;
-        acc[4] += x * v;
-        acc[5] += a.drc[(long)r * a.ld_x + c];
-        acc[6] += a.dcr[(long)r * a.ld_x + c];
-    }
+    if (a.f16)
+        stat_units<true>(a, acc);
+    else
+        stat_units<false>(a, acc);
     for (int k = 0; k < kStats; ++k) red[threadIdx.x][k] = acc[k];
     __syncthreads();
     for (int w = kStatThreads / 2; w > 0; w >>= 1) {
@@ -182,14 +202,23 @@ __global__ __launch_bounds__(kBfTile * kBfTile) void snlm_bilateral_kernel(const
 }
 
 // out = theta1 f_rc + theta2 f_cr, in place over f_rc (eq. snlm).
-__global__ __launch_bounds__(256) void snlm_sure_combine(float* frc, int ld_rc, const float* fcr, int ld_x,
-                                                         int H, int W, const double* theta) {
-    const long n = (long)H * W;
+// Units of kStatCols columns of one row as in snlm_sure_stats, unit u to
+// block u mod gridDim.x; kStatThreads threads per block.
+__global__ __launch_bounds__(kStatThreads) void snlm_sure_combine(float* frc, int ld_rc, const float* fcr,
+                                                                  int ld_x, int H, int W, const double* theta) {
     const double t1 = theta[0], t2 = theta[1];
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        const int r = (int)(i / W), c = (int)(i % W);
-        float* p = frc + (long)r * ld_rc + c;
-        *p = (float)(t1 * (double)*p + t2 * (double)fcr[(long)r * ld_x + c]);
+    const int nch = (W + kStatCols - 1) / kStatCols;
+    const int units = H * nch;
+    for (int u = blockIdx.x; u < units; u += gridDim.x) {
+        const int r = u / nch;
+        const int c0 = (u - r * nch) * kStatCols + threadIdx.x;
+        float* pr = frc + (long)r * ld_rc;
+        const float* qr = fcr + (long)r * ld_x;
+#pragma unroll
+        for (int k = 0; k < kStatCols / kStatThreads; ++k) {
+            const int c = c0 + k * kStatThreads;
+            if (c < W) pr[c] = (float)(t1 * (double)pr[c] + t2 * (double)qr[c]);
+        }
     }
 }
 }  // namespace snlm
@@ -1971,9 +2000,10 @@ int sure_enqueue(snlm_ctx* c, const snlm_job* j, float sigma, float* dst, int ld
                                  vargs, 0, st));
     int ld_x = Wp, H = j->H, W = j->W;
     void* cargs[] = {(void*)&frc, (void*)&ld_rc, (void*)&fcr, (void*)&ld_x, (void*)&H, (void*)&W, (void*)&result};
-    const long npx = (long)H * W;
-    const int cgrid = (int)std::min<long>((npx + 255) / 256, 8192);
-    HIP_CHECK(c, hipLaunchKernel((const void*)&snlm::snlm_sure_combine, dim3(cgrid), dim3(256), cargs, 0, st));
+    const long units = (long)H * ((W + snlm::kStatCols - 1) / snlm::kStatCols);
+    const int cgrid = (int)std::min<long>(units, 8192);
+    HIP_CHECK(c, hipLaunchKernel((const void*)&snlm::snlm_sure_combine, dim3(cgrid), dim3(snlm::kStatThreads),
+                                 cargs, 0, st));
     if (theta || stats) {
         double host[9];
         HIP_CHECK(c, hipMemcpyAsync(host, result, sizeof(host), hipMemcpyDeviceToHost, st));
