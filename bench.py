@@ -16,12 +16,13 @@ arrivals, p50/p99 latency and Mpixel/s, against FIFO plain launches), the
 precision variants' throughput on 2048 x 2048 and 4096 x 4096 images (their
 error against the FP64 oracle is a GPU test), the SURE-optimal combination of
 the two orders on a 2048 x 2048 image (``sure_combination``), the recursive
-Gaussian patch kernel on a 2048 x 2048 image (``recursive_gaussian``), and the
+Gaussian patch kernel on a 2048 x 2048 image (``recursive_gaussian``), a
+256 x 256 x 256 volume (``volume``), and the
 FP64 oracle timed on the host cores on a bounded sample of the batch
 (``cpu_baseline``, the only part that runs the oracle).
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-serve] [--no-precision] [--no-sure]
-                    [--no-iir] [--iir-only] [--no-cpu]
+                    [--no-iir] [--iir-only] [--no-volume] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -524,6 +525,24 @@ def sure_combination(torch, snlm, n=2048, sigma=30.0):
     return rec
 
 
+# ------------------------------------------------------------------ volumes --
+def volume(torch, snlm, n=256, sigma=20.0):
+    """An n x n x n FP32 volume (smooth pattern plus noise), S=10, K=3, box,
+    h = 10 sigma: the 1D pass along x, y and z in turn (three launches),
+    Mvoxel/s of the whole call, events on the stream it runs on.  Parity
+    against the FP64 oracle is tests/test_gpu_volume.py."""
+    from paper_1407_2343_amd.synth import noisy_volume
+    x = torch.from_numpy(noisy_volume(n, n, n, sigma, seed=9001)).to("cuda:0")
+    out = torch.empty_like(x)
+    ctx = snlm.Context(arena_bytes=snlm.workspace3d_bytes(n, n, n) + (1 << 20))
+    rec = {"volume": "%dx%dx%d sigma=%g S=%d K=%d box h=10 sigma" % (n, n, n, sigma, S, K)}
+    for axes in ("xyz", "zyx"):
+        ms, _ = time_steps(torch, lambda: ctx.denoise3d(x, S, K, 10 * sigma, "box", axes, out=out), 10, 2)
+        rec[axes] = {"mvoxel_per_s": round(n ** 3 / ms / 1e3, 1), "ms": round(ms, 3)}
+    ctx.close()
+    return rec
+
+
 # ------------------------------------------------------- recursive Gaussian --
 def recursive_gaussian(torch, snlm, n=2048, sigma=30.0):
     """The Gaussian patch kernel by the recursive filter (kernel "gauss_iir")
@@ -632,6 +651,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sure", action="store_true")
     ap.add_argument("--no-iir", action="store_true")
+    ap.add_argument("--no-volume", action="store_true")
     ap.add_argument("--batch-waves", type=int, default=0, metavar="N",
                     help="use N persistent waves per SIMD for the batch instead of autotuning (counter runs)")
     ap.add_argument("--issue-rate", action="store_true",
@@ -642,6 +662,8 @@ def main():
                     help="print how the served kernels of a rocprofv3 kernel trace overlap in time (no GPU)")
     ap.add_argument("--iir-only", action="store_true",
                     help="run only the recursive-Gaussian section and print it")
+    ap.add_argument("--volume-only", action="store_true",
+                    help="run only the volume section and print it (kernel traces)")
     ap.add_argument("--sure-only", action="store_true",
                     help="run only the SURE-combination and SNLM[f] section and print it (kernel traces)")
     ap.add_argument("--plain-only", action="store_true",
@@ -687,6 +709,9 @@ def main():
         return
     if a.iir_only:
         print(json.dumps({"recursive_gaussian": recursive_gaussian(torch, snlm)}), flush=True)
+        return
+    if a.volume_only:
+        print(json.dumps({"volume": volume(torch, snlm)}), flush=True)
         return
     if a.sure_only:
         print(json.dumps({"sure_combination": sure_combination(torch, snlm)}), flush=True)
@@ -810,6 +835,9 @@ def main():
     if not a.no_iir:
         log("recursive gaussian")
         result["recursive_gaussian"] = recursive_gaussian(torch, snlm)
+    if not a.no_volume:
+        log("volume")
+        result["volume"] = volume(torch, snlm)
     if not a.no_cpu:
         log("cpu baseline")
         result["cpu_baseline"] = cpu_baseline(items)

@@ -75,6 +75,15 @@ def noisy_image(H: int, W: int, sigma: float, seed: int, texture: bool = True,
     return f.astype(dtype)
 
 
+def noisy_volume(D: int, H: int, W: int, sigma: float, seed: int) -> np.ndarray:
+    """A smooth D x H x W pattern (a sinusoid in x and y, a ramp in z) plus
+    N(0, sigma^2) noise, float32."""
+    rng = np.random.default_rng(seed)
+    z, y, x = np.meshgrid(np.arange(D), np.arange(H), np.arange(W), indexing="ij")
+    clean = 128 + 60 * np.sin(x / 7.0) * np.cos(y / 5.0) + 3.0 * z
+    return (clean + sigma * rng.standard_normal(clean.shape)).astype(np.float32)
+
+
 def noisy_line(N: int, sigma: float, seed: int) -> np.ndarray:
     """A 1D piecewise-constant signal in [0, 1] plus N(0, sigma^2) noise, float64."""
     rng = np.random.default_rng(seed)

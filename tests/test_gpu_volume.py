@@ -5,15 +5,13 @@ import pytest
 
 import oracle
 from gpu_helpers import TOL, max_abs, say
+from paper_1407_2343_amd.synth import noisy_volume
 
 pytestmark = pytest.mark.gpu
 
 
 def _vol(D, H, W, seed, sigma=20.0):
-    rng = np.random.default_rng(seed)
-    z, y, x = np.meshgrid(np.arange(D), np.arange(H), np.arange(W), indexing="ij")
-    clean = 128 + 60 * np.sin(x / 7.0) * np.cos(y / 5.0) + 3.0 * z
-    return (clean + sigma * rng.standard_normal(clean.shape)).astype(np.float32)
+    return noisy_volume(D, H, W, sigma, seed)
 
 
 @pytest.mark.parametrize("shape", [(6, 40, 33), (3, 17, 70), (20, 9, 12), (1, 1, 1), (70, 3, 5)])
