@@ -120,6 +120,58 @@ def test_sure_f16_input():
     ctx.close()
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_sure_pitched_views(dtype):
+    """Input and output as views into larger buffers: a base 3 elements past
+    a 16-byte boundary and odd pitches, so the row passes cannot stage the
+    input through LDS and the output goes out sample by sample.  The result
+    is bitwise that of the same image stored contiguously (same arithmetic,
+    other load and store paths), and within tolerance of the oracle."""
+    import torch
+    H, W = 77, 141
+    img = _noisy(H, W, 20.0, 61)
+    if dtype == "f16":
+        img = img.astype(np.float16)
+    x = torch.from_numpy(img).to("cuda:0")
+    big = torch.full((H + 5, W + 7), 3.0, dtype=x.dtype, device="cuda:0")
+    xv = big[2:2 + H, 3:3 + W]
+    xv.copy_(x)
+    obig = torch.full((H + 3, W + 9), -7.0, device="cuda:0")
+    ov = obig[1:1 + H, 5:5 + W]
+    ctx = _ctx()
+    ref_out, ref_theta, _ = ctx.denoise_sure(x, 7, 2, 160.0, 20.0, "box")
+    ref_out = ref_out.clone()
+    out, theta, _ = _check_against_oracle(ctx, xv, 7, 2, 160.0, 20.0, "box",
+                                          xr=x.cpu().numpy().astype(np.float64))
+    assert theta == ref_theta
+    assert torch.equal(out, ref_out)
+    ov_out, _, _ = ctx.denoise_sure(xv, 7, 2, 160.0, 20.0, "box", out=ov)
+    torch.cuda.synchronize()
+    assert torch.equal(ov, ref_out)
+    # nothing outside the output view was written
+    mask = torch.ones_like(obig, dtype=torch.bool)
+    mask[1:1 + H, 5:5 + W] = False
+    assert bool((obig[mask] == -7.0).all())
+    ctx.close()
+
+
+def test_sure_bench_image_whole():
+    """The SURE workload as the benchmark times it: a 2048 x 2048 image
+    (synthetic clean image plus noise, sigma 30, the benchmark's seed), S=10,
+    K=3, box, h = 10 sigma.  Every pixel of the combination and of f_cr
+    within 1e-3 of the FP64 oracle, both divergence planes within 2e-4
+    relative, theta and the seven sums as the oracle's."""
+    import torch
+    n, sigma = 2048, 30.0
+    rng = np.random.default_rng(6001)
+    f0 = clean_image(n, n, rng)
+    f = (f0 + sigma * rng.standard_normal(f0.shape)).astype(np.float32)
+    x = torch.from_numpy(f).to("cuda:0")
+    ctx = _ctx()
+    _check_against_oracle(ctx, x, 10, 3, 10 * sigma, sigma, "box")
+    ctx.close()
+
+
 def test_sure_larger_image():
     import torch
     sigma = 30.0
