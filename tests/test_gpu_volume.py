@@ -80,6 +80,25 @@ def test_volume_errors():
 
 
 @pytest.mark.parametrize("axes", ["xyz", "zyx"])
+def test_volume_bench_whole(axes):
+    """The volume workload as the benchmark times it: 256 x 256 x 256 FP32
+    (the benchmark's seed), S=10, K=3, box, h = 10 sigma, both axis orders;
+    every voxel within 1e-3 of the FP64 oracle."""
+    import torch
+    import paper_1407_2343_amd as snlm
+    v = noisy_volume(256, 256, 256, 20.0, 9001)
+    x = torch.from_numpy(v).to("cuda:0")
+    ctx = snlm.Context(arena_bytes=1 << 16)
+    y = ctx.denoise3d(x, 10, 3, 200.0, "box", axes)
+    torch.cuda.synchronize()
+    ref = oracle.snlm3d(v.astype(np.float64), 10, 3, 200.0, "box", axes)
+    err = max_abs(y.cpu().numpy(), ref)
+    say("bench volume", axes, "whole max-abs %.2e" % err)
+    assert err <= TOL
+    ctx.close()
+
+
+@pytest.mark.parametrize("axes", ["xyz", "zyx"])
 def test_volume_largest(axes):
     """A volume at the 2 GiB limit (511 x 1024 x 1024 FP32): its z lines
     reach byte offsets near 2^31.  Every z line carries the same signal f(z),
