@@ -139,6 +139,19 @@ def test_iir_full_size_image():
     ctx.close()
 
 
+@pytest.mark.parametrize("beta", [2.0, 8.0])
+def test_iir_bench_image_whole(beta):
+    """The recursive-Gaussian workload as the benchmark times it: the 2048 x
+    2048 image (sigma 30, the benchmark's seed), S = 10, h = 10 sigma
+    sqrt(sqrt(2 pi) beta / 7), row_col, at beta = 2 and 8; every pixel
+    against the oracle."""
+    from paper_1407_2343_amd.synth import noisy_image
+    ctx = _ctx(1 << 26)
+    img = noisy_image(2048, 2048, 30.0, seed=7001)
+    _check(ctx, img, 10, beta, 300.0 * math.sqrt(math.sqrt(2 * math.pi) * beta / 7.0))
+    ctx.close()
+
+
 def test_iir_close_to_exact_fir():
     """Within its approximation error the recursive kernel tracks the exact
     Gaussian FIR whose taps reach 3 beta (K = 6 at beta = 2): far closer than
