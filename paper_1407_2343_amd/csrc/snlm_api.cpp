@@ -38,9 +38,12 @@ __global__ void snlm_clear_counters(uint32_t* counters, int n) {
 }
 
 // Served jobs: copies between the caller's images and their arena slots, one
-// launch per round.  Block row y of the grid copies image y of the table; its
-// blocks stride over the rows, its threads over the elements of a row
-// (coalesced).  Elements are esz = 2 or 4 bytes.
+// launch per round.  Block row y of the grid copies image y of the table.
+// Both images contiguous (pitch = width) and 16-byte aligned: one linear run
+// of 16-byte vectors over the blocks and threads, four loads in flight per
+// thread, then the last few elements.  Otherwise the blocks stride over the
+// rows and the threads over the elements of a row (coalesced).  Elements are
+// esz = 2 or 4 bytes.
 struct CopyDesc {
     const void* src;
     void* dst;
@@ -49,6 +52,31 @@ struct CopyDesc {
 
 __global__ __launch_bounds__(256) void snlm_copy_images(const CopyDesc* tab) {
     const CopyDesc d = tab[blockIdx.y];
+    if (d.src_ld == d.cols && d.dst_ld == d.cols && (((uintptr_t)d.src | (uintptr_t)d.dst) & 15) == 0) {
+        const long nb = (long)d.rows * d.cols * d.esz;
+        const long nv = nb >> 4;
+        const uint4* s = (const uint4*)d.src;
+        uint4* t = (uint4*)d.dst;
+        const long step = (long)gridDim.x * blockDim.x;
+        long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+        for (; i + 3 * step < nv; i += 4 * step) {
+            const uint4 v0 = s[i], v1 = s[i + step], v2 = s[i + 2 * step], v3 = s[i + 3 * step];
+            t[i] = v0;
+            t[i + step] = v1;
+            t[i + 2 * step] = v2;
+            t[i + 3 * step] = v3;
+        }
+        for (; i < nv; i += step) t[i] = s[i];
+        const int rest = (int)((nb & 15) / d.esz);  // elements after the last whole vector
+        if (blockIdx.x == 0 && (int)threadIdx.x < rest) {
+            const long e = nv * 16 / d.esz + threadIdx.x;
+            if (d.esz == 4)
+                ((float*)d.dst)[e] = ((const float*)d.src)[e];
+            else
+                ((uint16_t*)d.dst)[e] = ((const uint16_t*)d.src)[e];
+        }
+        return;
+    }
     for (int r = blockIdx.x; r < d.rows; r += gridDim.x) {
         if (d.esz == 4) {
             const float* src = (const float*)d.src + (long)r * d.src_ld;

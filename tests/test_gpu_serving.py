@@ -85,6 +85,13 @@ def test_submit_many_device_latency_and_mix():
         dtype = torch.float16 if i % 5 == 0 else torch.float32
         x = torch.from_numpy(noisy_image(H, W, sig, 8200 + i)).to("cuda:0").to(dtype)
         o = torch.full((H, W), -1.0, device="cuda:0")
+        if i % 7 == 3:
+            # pitched, unaligned views: the slot copies go row by row
+            xb = torch.zeros((H, W + 5), dtype=dtype, device="cuda:0")
+            xb[:, 1:1 + W] = x
+            x = xb[:, 1:1 + W]
+            ob = torch.full((H, W + 3), -1.0, device="cuda:0")
+            o = ob[:, 2:2 + W]
         reqs.append((x, o, S, K, 10 * sig, kern, order))
         jobs.append(srv.job_for(x, o, S, K, 10 * sig, kern, order))
     torch.cuda.synchronize()
