@@ -377,6 +377,21 @@ def serving(torch, snlm, n_req=2000, rate_frac=0.7, seed=4000, check=32, fifo=Tr
     if not fifo:
         plain.close()
         return rec
+    # The same requests as one offline batched call (every class planned at
+    # once, nothing arriving over time, no slot copies), for scale: default
+    # waves per SIMD, then the batch autotuner's choice per class.
+    off_outs = [torch.empty_like(o) for o in outs]
+    off = snlm.Context(arena_bytes=sum(snlm.workspace_bytes(r["H"], r["W"]) for r in reqs) + (1 << 20))
+    off_jobs = snlm.job_array([off.job_for(x, o, r["S"], r["K"], 10.0 * r["sigma"], r["kernel"], r["order"])
+                               for x, o, r in zip(xs, off_outs, reqs)])
+    for key, tune in (("offline_batch", False), ("offline_batch_autotuned", True)):
+        if tune:
+            off.autotune_batch(off_jobs)
+        ms_off, _ = time_steps(torch, lambda: off.denoise_jobs(off_jobs), 5, 2)
+        rec[key + "_ms"] = round(ms_off, 3)
+        rec[key + "_mpx_per_s"] = round(total_px / ms_off / 1e3, 1)
+    off.close()
+    del off_outs
     # FIFO plain launches at the same arrival times
     for j in job_list[:64]:
         plain.denoise_job(j)
