@@ -1080,8 +1080,21 @@ void balance_pass(const std::vector<PieceSrc>& src, int P, std::vector<BatchTile
         total += w;
         if (!p.cut) biggest = std::max(biggest, w);
     }
-    double lo = std::max(total / P, biggest), hi = older > 0 ? 2.0 * (total + kSegOverhead) : total + kSegOverhead;
+    // The greedy fill leaves each worker short of its budget by less than a
+    // minimal piece plus an overhead, so the smallest feasible budget lies a
+    // few chunks above total / P: bracket it from there in doubling steps
+    // (the fill costs O(pieces + P), and a round of the serving loop plans
+    // two passes per kernel class on the host), then bisect to 0.25 chunk.
+    double lo = std::max(total / P, biggest), hi = lo;
     if (fill_workers(src, lo, nullptr, nullptr, older) > P) {
+        const double cap = older > 0 ? 2.0 * (total + kSegOverhead) : total + kSegOverhead;
+        double step = kMinPiece + 2.0 * kSegOverhead + 1.0;
+        for (;;) {
+            hi = std::min(lo + step, cap);
+            if (hi >= cap || fill_workers(src, hi, nullptr, nullptr, older) <= P) break;
+            lo = hi;
+            step *= 2.0;
+        }
         for (int it = 0; it < 40 && hi - lo > 0.25; ++it) {
             const double mid = 0.5 * (lo + hi);
             if (fill_workers(src, mid, nullptr, nullptr, older) <= P)
@@ -1089,8 +1102,6 @@ void balance_pass(const std::vector<PieceSrc>& src, int P, std::vector<BatchTile
             else
                 lo = mid;
         }
-    } else {
-        hi = lo;
     }
     first.clear();
     fill_workers(src, hi, &tiles, &first, older);
@@ -1099,12 +1110,14 @@ void balance_pass(const std::vector<PieceSrc>& src, int P, std::vector<BatchTile
     first[P] = (uint32_t)tiles.size();
 }
 
-// Waves per SIMD of the persistent launches of a class (autotuned, default 1:
-// one wave per SIMD already keeps the VALU busy when the work is balanced).
+// Waves per SIMD of the persistent launches of a class (autotuned; default
+// 2, capped by the kernel's occupancy: with the older wave of each SIMD given
+// two thirds of the pair's work, two waves issue more of the exp-bearing pair
+// body than one).
 int batch_waves(snlm_ctx* c, const ClassKey& key) {
     std::lock_guard<std::mutex> g(c->tune_mu);
     auto it = c->batch_tuned.find(key);
-    return it != c->batch_tuned.end() ? it->second : 1;
+    return it != c->batch_tuned.end() ? it->second : 2;
 }
 
 int batch_workers(snlm_ctx* c, const void* fn, int waves_per_simd) {
