@@ -362,8 +362,9 @@ int snlm_autotune(snlm_ctx *ctx, const snlm_job *probe, int *best);
 /* Selects the number of persistent waves per SIMD (1..4, within the kernel's
  * occupancy) of batched launches for the kernel classes of these jobs, timing
  * each candidate on the jobs themselves (their outputs are overwritten), and
- * remembers it for later batches of the same classes.  Results do not depend
- * on the choice.  *best receives it. */
+ * remembers it for later batches of the same classes (untuned classes run two
+ * waves per SIMD, or fewer where the kernel's occupancy is lower).  Results do
+ * not depend on the choice.  *best receives it. */
 int snlm_autotune_batch(snlm_ctx *ctx, const snlm_job *jobs, int n, int *best);
 
 /* Saves / loads the autotuner's choices as a small JSON file. */
