@@ -9,7 +9,8 @@
 * precision: FP16/FP32 storage x block/plain/Kahan running sums on the
   2048 x 2048 and 4096 x 4096 images, every pixel against the oracle.
 * the benchmark's batch as timed: all 64 images bitwise equal to their plain
-  launches and within 1e-3 of the oracle at every pixel.
+  launches and within 1e-3 of the oracle at every pixel; the same images as
+  FP16 with the Gaussian kernel in col_row order, likewise.
 """
 import math
 import os
@@ -350,6 +351,32 @@ def test_bench_batch_workload_whole():
         ref = oracle.snlm(img.astype(np.float64), 10, 3, 10.0 * sig, "box", "row_col")
         worst = max(worst, max_abs(o.cpu().numpy(), ref))
     say("  whole-image max-abs over the 64 images", worst)
+    assert worst <= TOL
+    ctx.close()
+
+
+def test_bench_batch_workload_gauss_f16_whole():
+    """The benchmark's 64 ragged images with the other kernel, order and
+    storage: FP16 inputs, Gaussian patch kernel (beta = K / 2), col_row, S=10,
+    K=3, default waves.  Every output bitwise equal to its plain launch and
+    within 1e-3 of the FP64 oracle (run on the FP16 values) at every pixel."""
+    import torch
+    import paper_1407_2343_amd as snlm
+    from paper_1407_2343_amd.synth import batch_workload
+    items = batch_workload(64, 128, 1024, seed=2000)
+    xs = [torch.from_numpy(img.astype(np.float16)).to("cuda:0") for img, _ in items]
+    outs = [torch.full(x.shape, -3.0, device="cuda:0") for x in xs]
+    ctx = _ctx(sum(snlm.workspace_bytes(*x.shape) for x in xs) + (1 << 20))
+    jobs = snlm.job_array([ctx.job_for(x, o, 10, 3, 10.0 * sig, "gauss", "col_row")
+                           for x, o, (_, sig) in zip(xs, outs, items)])
+    ctx.denoise_jobs(jobs, sync=True)
+    worst = 0.0
+    for i, ((img, sig), x, o) in enumerate(zip(items, xs, outs)):
+        alone = ctx.denoise(x, 10, 3, 10.0 * sig, "gauss", "col_row", sync=True)
+        assert torch.equal(alone, o), i
+        ref = oracle.snlm(x.cpu().numpy().astype(np.float64), 10, 3, 10.0 * sig, "gauss", "col_row")
+        worst = max(worst, max_abs(o.cpu().numpy(), ref))
+    say("  gauss col_row FP16 batch: whole-image max-abs over the 64 images", worst)
     assert worst <= TOL
     ctx.close()
 
