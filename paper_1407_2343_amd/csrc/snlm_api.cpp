@@ -1036,6 +1036,21 @@ int fill_workers(const std::vector<PieceSrc>& src, double W0, std::vector<BatchT
         int pos = p.c0;
         while (pos < p.c1) {
             const int r = p.c1 - pos;
+            if (!out && p.cut && cur == 0.0) {
+                // Counting only: a fresh worker facing a cut-able rest of at
+                // least kw + kMinPiece chunks takes kw = floor(W - overhead)
+                // of them (the rest cannot fit), and so does every following
+                // worker of the same budget while that holds, m times in all.
+                const int kw = (int)std::floor(W - kSegOverhead);
+                if (kw >= kMinPiece && r >= kw + kMinPiece) {
+                    int m = (r - kMinPiece) / kw;
+                    if (older > 0 && workers <= older) m = std::min(m, older - workers + 1);
+                    pos += m * kw;
+                    workers += m;
+                    W = budget(workers);
+                    continue;
+                }
+            }
             const double rem = W - cur;
             if (r + kSegOverhead <= rem + 1e-9) {
                 emit(p, pos, p.c1);
@@ -1104,6 +1119,8 @@ void balance_pass(const std::vector<PieceSrc>& src, int P, std::vector<BatchTile
         }
     }
     first.clear();
+    first.reserve((size_t)P + 2);
+    tiles.reserve(src.size() + (size_t)P + 1);
     fill_workers(src, hi, &tiles, &first, older);
     while ((int)first.size() < P + 1) first.push_back((uint32_t)tiles.size());
     first.resize(P + 1);
