@@ -1127,6 +1127,37 @@ void balance_pass(const std::vector<PieceSrc>& src, int P, std::vector<BatchTile
     first[P] = (uint32_t)tiles.size();
 }
 
+// The hardware hands workgroup k to XCD k mod kXcds.  Consecutive shares meet
+// inside a line group (the later one re-reads the samples before its cut), so
+// they go to workgroups of one XCD, whose L2 may still hold them: within each
+// class of n workgroups (the first and the second wave of every SIMD when the
+// shares are 2 : 1, else all P), share i of the class runs on workgroup
+// (i mod (n / kXcds)) kXcds + i / (n / kXcds).  The tiles are reordered so that
+// every workgroup's tiles stay contiguous.  Results do not depend on it.
+constexpr int kXcds = 8;
+
+void xcd_order(std::vector<BatchTile>& tiles, std::vector<uint32_t>& first, int n) {
+    const int P = (int)first.size() - 1;
+    if (n <= 0 || n % kXcds != 0 || P % n != 0) return;
+    const int per = n / kXcds;
+    std::vector<int> share_of(P);  // share run by workgroup k
+    for (int w = 0; w < P; ++w) {
+        const int base = w / n * n, i = w - base;
+        share_of[base + (i % per) * kXcds + i / per] = w;
+    }
+    std::vector<BatchTile> out;
+    out.reserve(tiles.size());
+    std::vector<uint32_t> f(P + 1);
+    for (int k = 0; k < P; ++k) {
+        f[k] = (uint32_t)out.size();
+        const int w = share_of[k];
+        out.insert(out.end(), tiles.begin() + first[w], tiles.begin() + first[w + 1]);
+    }
+    f[P] = (uint32_t)out.size();
+    tiles.swap(out);
+    first.swap(f);
+}
+
 // Waves per SIMD of the persistent launches of a class (autotuned; default
 // 2, capped by the kernel's occupancy: with the older wave of each SIMD given
 // two thirds of the pair's work, two waves issue more of the exp-bearing pair
@@ -1204,6 +1235,7 @@ void plan_classes(snlm_ctx* c, const std::vector<const snlm_job*>& jobs,
             const int nsimd = 4 * std::max(c->num_cu, 1);
             const int older = (waves == 2 && P == 2 * nsimd) ? nsimd : 0;
             balance_pass(src, P, tiles, cp.first[p], older);
+            if (c->batch_split) xcd_order(tiles, cp.first[p], older > 0 ? older : P);
             for (auto& f : cp.first[p]) f += (uint32_t)before;
             for (const BatchTile& t : tiles) cp.jobs[t.job].tiles[p] += 1;
             if (!c->batch_split)  // claimed launches: longest tiles first
